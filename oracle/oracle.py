@@ -69,43 +69,66 @@ _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 _u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
 
 
+def _bind(path: str):
+    L = C.CDLL(path)
+    ev = [_f32p, _f32p, _f32p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_float]
+    L.orc_depth.argtypes = [C.c_float, C.c_float, C.c_float]
+    L.orc_depth.restype = C.c_int
+    L.orc_grid_d.argtypes = [C.c_float, C.c_float, C.c_int, C.c_int64]
+    L.orc_grid_d.restype = C.c_float
+    L.orc_rate.argtypes = [C.c_float, C.c_float]
+    L.orc_rate.restype = C.c_float
+    L.orc_pixels.argtypes = ev + [C.c_float, _i32p]
+    L.orc_pixels.restype = None
+    L.orc_point.argtypes = ev + [C.c_float, C.POINTER(C.c_uint64), C.POINTER(C.c_int64), C.c_void_p]
+    L.orc_point.restype = C.c_int
+    L.orc_bound.argtypes = ev + [C.c_float, C.c_float, C.POINTER(C.c_uint64),
+                                 C.POINTER(C.c_int64), C.c_void_p]
+    L.orc_bound.restype = C.c_int
+    L.orc_bnb.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.c_double, C.c_int64,
+                               C.POINTER(OrcResult)]
+    L.orc_bnb.restype = C.c_int
+    L.orc_bnb64.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.c_double, C.c_int64,
+                                 C.POINTER(OrcResult), C.POINTER(C.c_double)]
+    L.orc_bnb64.restype = C.c_int
+    L.orc_dense.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.POINTER(OrcResult),
+                                 C.c_void_p, C.c_void_p]
+    L.orc_dense.restype = C.c_int
+    L.orc_point64.argtypes = ev + [C.c_double, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
+    L.orc_point64.restype = C.c_int
+    L.orc_select.argtypes = [_f64p, C.c_int64, C.c_double, C.c_double, _i64p, _f32p]
+    L.orc_select.restype = C.c_int64
+    L.orc_downsample.argtypes = [_f32p, _f32p, C.c_int64, C.c_int, C.c_int, C.c_int, _u16p]
+    L.orc_downsample.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        ev = [_f32p, _f32p, _f32p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_float]
-        L.orc_depth.argtypes = [C.c_float, C.c_float, C.c_float]
-        L.orc_depth.restype = C.c_int
-        L.orc_grid_d.argtypes = [C.c_float, C.c_float, C.c_int, C.c_int64]
-        L.orc_grid_d.restype = C.c_float
-        L.orc_rate.argtypes = [C.c_float, C.c_float]
-        L.orc_rate.restype = C.c_float
-        L.orc_pixels.argtypes = ev + [C.c_float, _i32p]
-        L.orc_pixels.restype = None
-        L.orc_point.argtypes = ev + [C.c_float, C.POINTER(C.c_uint64), C.POINTER(C.c_int64), C.c_void_p]
-        L.orc_point.restype = C.c_int
-        L.orc_bound.argtypes = ev + [C.c_float, C.c_float, C.POINTER(C.c_uint64),
-                                     C.POINTER(C.c_int64), C.c_void_p]
-        L.orc_bound.restype = C.c_int
-        L.orc_bnb.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.c_double, C.c_int64,
-                                   C.POINTER(OrcResult)]
-        L.orc_bnb.restype = C.c_int
-        L.orc_bnb64.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.c_double, C.c_int64,
-                                     C.POINTER(OrcResult), C.POINTER(C.c_double)]
-        L.orc_bnb64.restype = C.c_int
-        L.orc_dense.argtypes = ev + [C.c_float, C.c_float, C.c_float, C.POINTER(OrcResult),
-                                     C.c_void_p, C.c_void_p]
-        L.orc_dense.restype = C.c_int
-        L.orc_point64.argtypes = ev + [C.c_double, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
-        L.orc_point64.restype = C.c_int
-        L.orc_select.argtypes = [_f64p, C.c_int64, C.c_double, C.c_double, _i64p, _f32p]
-        L.orc_select.restype = C.c_int64
-        L.orc_downsample.argtypes = [_f32p, _f32p, C.c_int64, C.c_int, C.c_int, C.c_int, _u16p]
-        L.orc_downsample.restype = C.c_int
-        _lib = L
+        _lib = _bind(LIB)
     return _lib
+
+
+class using:
+    """Context manager that points this module at another build of the oracle
+    (a copy with a planted mistake, in the tests that show the pins catch it)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib
+        self.prev = lib()
+        _lib = _bind(self.path)
+        return self
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.prev
+        return False
 
 
 def _f32(a):

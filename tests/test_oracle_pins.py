@@ -190,6 +190,46 @@ def test_bound_equals_point_at_singletons(orc):
         assert (Sb, Nl) == (S, N) and np.array_equal(Hb, Hp)
 
 
+def test_bound_valid_near_pixel_corners(orc):
+    """Eq. (18) where fp32 rounding matters most: rays that pass within about
+    an ulp of a pixel corner, probed at every fp32 d near the crossing.  The
+    rounded warped point can land on either side of the corner, and the
+    bound must still cover it."""
+    W = H = 128
+    cx = cy = 64.0
+    tau = 0.5
+    rng = np.random.default_rng(21)
+    n = 400
+    # a corner (X, Y) and a point on the FOE-corner ray, nudged sideways
+    X = rng.integers(70, 120, n).astype(np.float64)
+    Y = rng.integers(70, 120, n).astype(np.float64)
+    frac = rng.uniform(0.55, 0.9, n)
+    px = cx + (X - cx) * frac
+    py = cy + (Y - cy) * frac
+    x = px.astype(np.float32)
+    y = py.astype(np.float32)
+    t = rng.uniform(0.0, 0.2, n).astype(np.float32)
+    misses = 0
+    for i in range(n):
+        ev = orc.Events(x[i:i + 1], y[i:i + 1], t[i:i + 1], tau, W, H, (cx, cy))
+        delta = np.float32(tau) - t[i]
+        ax = np.float32(np.float32(x[i] - np.float32(cx)) * delta)
+        rc = (X[i] - float(x[i])) / float(ax)
+        dc = rc / (1.0 + rc * tau)
+        if not (0.0 < dc < 1.9):
+            continue
+        d_a, d_b = float(np.float32(dc * 0.98)), float(np.float32(min(dc * 1.02, 1.99)))
+        _, _, Hb = orc.bound(ev, d_a, d_b, want_image=True)
+        lo = np.array([dc * (1 - 2e-6)], np.float32).view(np.uint32)[0]
+        hi = np.array([dc * (1 + 2e-6)], np.float32).view(np.uint32)[0]
+        for bits in range(int(lo), int(hi) + 1):
+            d = float(np.array([bits], np.uint32).view(np.float32)[0])
+            p = orc.pixels(ev, d)[0]
+            if p >= 0 and Hb[p] == 0:
+                misses += 1
+    assert misses == 0
+
+
 def _pixel_segment_distance(px, py, ax0, ay0, bx0, by0):
     """Distance from the closed unit square [px, px+1] x [py, py+1] to the
     segment A-B (fp64; sampled finely along the segment)."""
