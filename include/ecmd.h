@@ -1,0 +1,230 @@
+/*
+ * ecmd.h - C ABI of the MI355X exact event-based divergence estimator.
+ *
+ * Method: "Globally Optimal Event-Based Divergence Estimation for Ventral
+ * Landing" (arXiv 2209.13168).  Given the events of a window of length tau,
+ * the library finds the divergence d = -nu (Z0 = 1, Sec. 4.1) that maximises
+ * the contrast of the motion-compensated event image (Sec. 4.2, eqs.
+ * (12)-(14)) with the branch and bound of Algorithm 1 and the upper bound of
+ * Sec. 4.3 (eqs. (15)-(20)), on the GPU.
+ *
+ * Fixed readings of the method (identical to the library's CPU reference):
+ *   - fp32 warp in this order: per event ax = (x - cx)(tau - t'),
+ *     ay = (y - cy)(tau - t'); per hypothesis r = d / (1 - d tau);
+ *     xw = fmaf(ax, r, x), yw = fmaf(ay, r, y) (eq. (12));
+ *   - pixel k covers [k, k+1); an event counts iff 0 <= xw < W, 0 <= yw < H;
+ *   - contrast key K = M*S - N^2 = M^2 C (eq. (14)), S = sum H^2,
+ *     N = sum H, M = W*H; bound key K_bar = M*S_bar - N_low^2 (eq. (15)),
+ *     S_bar from the upper-bound image of eq. (17) and N_low from eq. (20);
+ *   - candidates: the dyadic grid d_j = float(d_lo + (d_hi - d_lo) j 2^-L),
+ *     j = 1 .. 2^L - 1, with L the smallest depth whose spacing is <= eps;
+ *   - the result is the largest K, ties to the smallest j (gamma = 0), or
+ *     Algorithm 1's gamma-optimal stop (gamma > 0).
+ *
+ * Conventions for every entry point:
+ *   - return 0 (ECMD_OK) or a negative ECMD_E* code; ecmd_last_error(ctx)
+ *     then holds a message.  On error, outputs are left untouched except
+ *     the status fields of result structs;
+ *   - array arguments are host pointers unless `flags & ECMD_DEVICE_PTR`,
+ *     in which case every array argument of that call (inputs and array
+ *     outputs, not the result structs) is a device pointer on the context's
+ *     device.  The caller owns all arrays; they are only borrowed for the
+ *     duration of the call.  Result structs are always host memory;
+ *   - calls are synchronous with respect to the host and are ordered on the
+ *     context's HIP stream;
+ *   - a context is not thread-safe: use one per host thread.
+ */
+#ifndef ECMD_H
+#define ECMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ECMD_OK 0
+#define ECMD_EINVAL (-1)    /* invalid argument (message says which) */
+#define ECMD_ENOMEM (-2)    /* device or host allocation failed */
+#define ECMD_EDEVICE (-3)   /* HIP runtime error (message has the HIP text) */
+#define ECMD_EBUDGET (-4)   /* node budget reached: incumbent + certified gap */
+#define ECMD_EFRONTIER (-5) /* frontier capacity exceeded (per window) */
+
+#define ECMD_DEVICE_PTR 1u
+
+typedef struct ecmd_ctx ecmd_ctx;
+
+/* Sensor geometry.  The focus of expansion (foe_x, foe_y) is the principal
+ * point (the FOE of Sec. 3.2), in pixel coordinates where pixel k covers
+ * [k, k+1).  An integer FOE strictly inside the sensor lets the library cut
+ * the image into quadrants that no event ever leaves. */
+typedef struct {
+    int32_t width, height;
+    float foe_x, foe_y;
+} ecmd_sensor;
+
+/* Events of a stream, structure of arrays.  t is absolute time in seconds
+ * (sorted is not required).  Polarity is not used (Sec. 4.2). */
+typedef struct {
+    const float *x;
+    const float *y;
+    const double *t;
+    int64_t n;
+} ecmd_events;
+
+/* Window [t0, t1] (closed): the batch of Sec. 3.3, tau = float(t1 - t0). */
+typedef struct {
+    double t0, t1;
+} ecmd_window;
+
+/* Search: d in [d_lo, d_hi] with grid spacing <= eps (0 <= d_lo < d_hi,
+ * float(d_hi * tau) < 1: the cheirality limit of eq. (11)).  gamma > 0 stops
+ * Algorithm 1 once the best bound is within gamma of the incumbent in
+ * contrast units.  max_nodes > 0 caps node expansions (ECMD_EBUDGET).
+ * frontier_batch caps the nodes expanded together per step (0 = library
+ * default); frontier_capacity caps queued nodes per window (0 = default). */
+typedef struct {
+    float d_lo, d_hi, eps;
+    float reserved0;
+    double gamma;
+    int64_t max_nodes;
+    int32_t frontier_batch;
+    int32_t frontier_capacity;
+} ecmd_search;
+
+/* Per-window result.  K = K_hi * 2^64 + K_lo is the exact contrast key of
+ * the returned grid point; contrast = K / M^2; d_end = d_hat/(1 - d_hat tau)
+ * is the divergence at the window end (Sec. 4.1's point estimate with
+ * nu = -d_hat).  gap is 0 when the result is certified optimal; otherwise
+ * an upper bound on (best contrast - returned contrast).  Counters:
+ * event_hyp_evals = sum over evaluated hypotheses of the window's event
+ * count; pixel_updates = upper-bound image increments. */
+typedef struct {
+    int32_t status;
+    uint32_t j_star;
+    uint32_t L;
+    float d_hat;
+    double contrast;
+    double d_end;
+    double gap;
+    uint64_t K_lo;
+    int64_t K_hi;
+    int64_t n_events;
+    int64_t nodes_expanded;
+    int64_t nodes_pruned;
+    int64_t point_evals;
+    int64_t bound_evals;
+    int64_t event_hyp_evals;
+    int64_t pixel_updates;
+    int32_t steps;
+    int32_t seeded;
+} ecmd_result;
+
+/* ------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The context owns all
+ * device scratch; ecmd_ctx_destroy frees it. */
+int ecmd_ctx_create(ecmd_ctx **out, int device, void *hip_stream);
+void ecmd_ctx_destroy(ecmd_ctx *ctx);
+/* Last error message of this context ("" if none). */
+const char *ecmd_last_error(const ecmd_ctx *ctx);
+/* Library version string. */
+const char *ecmd_version(void);
+
+/* ---------------------------------------------------------- estimation */
+
+/* One window (Algorithm 1 on the events with t in [t0, t1]).  d_seed
+ * (nullable, host) is a starting incumbent proposal: its nearest grid point
+ * is evaluated first.  It can only speed pruning; the result is unchanged. */
+int ecmd_estimate_divergence(ecmd_ctx *ctx, const ecmd_sensor *sensor,
+                             const ecmd_events *events, ecmd_window window,
+                             const ecmd_search *search, uint32_t flags,
+                             const float *d_seed, ecmd_result *out);
+
+/* B windows in one launch sequence.  Window b holds the events
+ * [offsets[b], offsets[b+1]) of x, y, t_rel, with t_rel the offset from the
+ * window start (0 <= t_rel <= tau[b]).  offsets (B+1, non-decreasing, int64)
+ * and tau (B) follow `flags` like the event arrays.  d_seeds (nullable, B
+ * values, NaN = none) follow `flags` too.  out[b].status reports per-window
+ * budget/frontier outcomes; the call returns the first such status, or a
+ * negative code for a call-level error (nothing computed). */
+int ecmd_estimate_divergence_batched(ecmd_ctx *ctx, const ecmd_sensor *sensor,
+                                     const float *x, const float *y,
+                                     const float *t_rel, const int64_t *offsets,
+                                     const float *tau, int32_t B,
+                                     const ecmd_search *search, uint32_t flags,
+                                     const float *d_seeds, ecmd_result *out);
+
+/* -------------------------------------------------------------- probes */
+
+/* Pixel index ky*W + kx of every event at divergence d (-1 = outside),
+ * eqs. (12)-(13). */
+int ecmd_probe_pixels(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
+                      const float *y, const float *t_rel, int64_t n, float tau,
+                      float d, uint32_t flags, int32_t *pix_out);
+
+/* Point values (S_k, N_k) of m divergences d[k] (eqs. (13)-(14)); when
+ * img_out is non-null it receives the m event images H (m*W*H uint32). */
+int ecmd_probe_point(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
+                     const float *y, const float *t_rel, int64_t n, float tau,
+                     const float *d, int32_t m, uint32_t flags, uint64_t *S,
+                     int64_t *N, uint32_t *img_out);
+
+/* Interval values (S_bar_k, N_low_k) of m intervals [d_a[k], d_b[k]]
+ * (eqs. (17)-(20)); img_out (nullable) receives the m upper-bound images.
+ * The search range [d_lo, d_hi] bounds every interval (it sets the event
+ * binning); pass the range the intervals come from. */
+int ecmd_probe_bound(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
+                     const float *y, const float *t_rel, int64_t n, float tau,
+                     float d_lo, float d_hi, const float *d_a, const float *d_b,
+                     int32_t m, uint32_t flags, uint64_t *S_bar, int64_t *N_low,
+                     uint32_t *img_out);
+
+/* ------------------------------------------------ learned incumbent */
+
+typedef struct ecmd_cnn ecmd_cnn;
+
+/* Input of the proposal network: the unwarped (d = 0) event counts of each
+ * window on a 64x64 grid (cell floor(float(x*64)/W), clamped to 63), scaled
+ * by 4096/N and rounded to bfloat16 (round to nearest even); out holds
+ * B*64*64 uint16 bfloat16 bit patterns.  Windows as in the batched call. */
+int ecmd_downsample(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
+                    const float *y, const int64_t *offsets, int32_t B,
+                    uint32_t flags, uint16_t *out);
+
+/* Network: conv3x3/s2 1->16, ReLU, conv3x3/s2 16->32, ReLU, conv3x3/s2
+ * 32->64, ReLU, global average pool, linear 64->1 (23,361 parameters).
+ * Activations and weights are rounded to bfloat16 at each layer input;
+ * products accumulate in fp32.  Parameters are fp32 masters (Adam). */
+#define ECMD_CNN_NPARAM 23361
+int ecmd_cnn_create(ecmd_ctx *ctx, uint64_t seed, ecmd_cnn **out);
+void ecmd_cnn_destroy(ecmd_cnn *cnn);
+/* Copy the fp32 parameter vector (ECMD_CNN_NPARAM values, host). */
+int ecmd_cnn_get_params(ecmd_cnn *cnn, float *host_params);
+int ecmd_cnn_set_params(ecmd_cnn *cnn, const float *host_params);
+/* Forward pass on B images (bf16 bits, B*64*64): d_out[b] (fp32). */
+int ecmd_cnn_forward(ecmd_cnn *cnn, const uint16_t *imgs, int32_t B, uint32_t flags,
+                     float *d_out);
+/* Mean squared error against labels and its gradient w.r.t. the
+ * parameters (host, ECMD_CNN_NPARAM values). */
+int ecmd_cnn_grads(ecmd_cnn *cnn, const uint16_t *imgs, const float *labels, int32_t B,
+                   uint32_t flags, float *grad_out, float *loss_out);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the MSE loss. */
+int ecmd_cnn_train_step(ecmd_cnn *cnn, const uint16_t *imgs, const float *labels,
+                        int32_t B, float lr, uint32_t flags, float *loss_out);
+
+/* Batched estimation seeded by the network: downsample -> forward -> the
+ * predicted d seeds each window's incumbent -> certified branch and bound.
+ * Same arguments and results as ecmd_estimate_divergence_batched. */
+int ecmd_estimate_divergence_learned(ecmd_ctx *ctx, ecmd_cnn *cnn,
+                                     const ecmd_sensor *sensor, const float *x,
+                                     const float *y, const float *t_rel,
+                                     const int64_t *offsets, const float *tau,
+                                     int32_t B, const ecmd_search *search,
+                                     uint32_t flags, ecmd_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECMD_H */

@@ -1,0 +1,795 @@
+// Host runtime and C ABI of the MI355X divergence estimator.
+//
+// One call = prep (tile binning of every window's events, a1) -> init of the
+// per-window branch and bound (Alg. 1) -> repeated [evaluate hypotheses
+// (a2, a3), frontier step (a4)] until every window is certified.  All
+// search state stays in device memory; the host only launches and polls a
+// single counter of windows still running.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "ecmd.h"
+#include "ecmd_internal.hpp"
+
+using namespace ecmd;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max(bytes, (size_t)256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct HostBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap) return hipSuccess;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max(bytes, (size_t)256);
+        hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+        if (e == hipSuccess) cap = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+constexpr int kChunk = 4096;          // events per prep workgroup
+constexpr int kDefaultF = 64;         // nodes expanded together
+constexpr int kDefaultCap = 16384;    // queued nodes per window
+constexpr int kMaxSteps = 1 << 20;    // hard stop of the step loop
+
+}  // namespace
+
+struct ecmd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int num_cu = 0;
+    size_t max_lds = 0;
+    // staging of host inputs
+    DevBuf sx, sy, st, soff, stau, sseed;
+    // prep
+    DevBuf wp, blk, cnt_own, cnt_guest, seg_off, seg_own, cursor, ev, err_flag;
+    // search
+    DevBuf state, front, sel, hyps, items, queues, part, n_active;
+    // probes / window selection / downsample
+    DevBuf pix, img, keep, counts, misc;
+    HostBuf pinned;
+    std::vector<long long> h_off;
+    std::vector<float> h_tau;
+};
+
+struct ecmd_cnn;  // defined in ecmd_cnn.hip
+
+static int fail(ecmd_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? ECMD_ENOMEM : ECMD_EDEVICE,       \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+// ---------------------------------------------------------------- helpers
+
+// Grid point j of depth L (fp64 then fp32; identical to the device's).
+static float host_grid_d(float d_lo, float d_hi, int L, unsigned j) {
+    double span = (double)d_hi - (double)d_lo;
+    double v = (double)d_lo + span * ldexp((double)j, -L);
+    return (float)v;
+}
+
+static int grid_depth(float d_lo, float d_hi, float eps) {
+    double span = (double)d_hi - (double)d_lo;
+    for (int L = 1; L <= 30; ++L)
+        if (ldexp(span, -L) <= (double)eps) return L;
+    return -1;
+}
+
+// Tile plan: column and row cuts at the FOE lines when the FOE is an
+// integer point strictly inside the sensor (no event crosses them), then
+// each band split evenly until every tile fits the LDS budget.
+static bool plan_geometry(int W, int H, float cx, float cy, int max_px, Geometry& g) {
+    memset(&g, 0, sizeof g);
+    g.W = W;
+    g.H = H;
+    g.cx = cx;
+    g.cy = cy;
+    std::vector<int> bx = {0}, by = {0};
+    if (cx == floorf(cx) && cx > 0.0f && cx < (float)W) bx.push_back((int)cx);
+    if (cy == floorf(cy) && cy > 0.0f && cy < (float)H) by.push_back((int)cy);
+    bx.push_back(W);
+    by.push_back(H);
+    auto split = [](const std::vector<int>& base, int k) {
+        std::vector<int> cut;
+        for (size_t b = 0; b + 1 < base.size(); ++b) {
+            int a = base[b], e = base[b + 1];
+            for (int i = 0; i < k; ++i) cut.push_back(a + (int)((long long)(e - a) * i / k));
+        }
+        cut.push_back(base.back());
+        return cut;
+    };
+    auto max_band = [](const std::vector<int>& cut) {
+        int m = 0;
+        for (size_t i = 0; i + 1 < cut.size(); ++i) m = std::max(m, cut[i + 1] - cut[i]);
+        return m;
+    };
+    int best = -1;
+    std::vector<int> bc, br;
+    for (int kx = 1; kx <= 32; ++kx) {
+        for (int ky = 1; ky <= 32; ++ky) {
+            std::vector<int> c = split(bx, kx), r = split(by, ky);
+            int ntx = (int)c.size() - 1, nty = (int)r.size() - 1;
+            if (ntx * nty > kMaxTiles) continue;
+            if ((long long)max_band(c) * max_band(r) > max_px) continue;
+            // fewest tiles, then the squarest
+            int score = ntx * nty * 1000 + std::abs(max_band(c) - max_band(r)) % 1000;
+            if (best < 0 || score < best) {
+                best = score;
+                bc = c;
+                br = r;
+            }
+        }
+    }
+    if (best < 0) return false;
+    g.ntx = (int)bc.size() - 1;
+    g.nty = (int)br.size() - 1;
+    g.T = g.ntx * g.nty;
+    for (int i = 0; i <= g.ntx; ++i) g.colcut[i] = bc[i];
+    for (int i = 0; i <= g.nty; ++i) g.rowcut[i] = br[i];
+    g.max_tile_px = max_band(bc) * max_band(br);
+    return true;
+}
+
+static int check_sensor(ecmd_ctx* c, const ecmd_sensor* s) {
+    if (!s) return fail(c, ECMD_EINVAL, "sensor is NULL");
+    if (s->width <= 0 || s->height <= 0 || s->width > 32768 || s->height > 32768)
+        return fail(c, ECMD_EINVAL, "sensor size %dx%d out of range", s->width, s->height);
+    if (!isfinite(s->foe_x) || !isfinite(s->foe_y)) return fail(c, ECMD_EINVAL, "FOE is not finite");
+    return ECMD_OK;
+}
+
+static int check_search(ecmd_ctx* c, const ecmd_search* s, int* L) {
+    if (!s) return fail(c, ECMD_EINVAL, "search is NULL");
+    if (!isfinite(s->d_lo) || !isfinite(s->d_hi) || !(s->d_lo >= 0.0f) || !(s->d_lo < s->d_hi))
+        return fail(c, ECMD_EINVAL, "need 0 <= d_lo < d_hi (got %g, %g)", s->d_lo, s->d_hi);
+    if (!(s->eps > 0.0f) || !isfinite(s->eps)) return fail(c, ECMD_EINVAL, "eps must be > 0");
+    *L = grid_depth(s->d_lo, s->d_hi, s->eps);
+    if (*L < 1) return fail(c, ECMD_EINVAL, "eps too small for range (depth > 30)");
+    if (!(s->gamma >= 0.0) || !isfinite(s->gamma)) return fail(c, ECMD_EINVAL, "gamma must be >= 0");
+    if (s->max_nodes < 0) return fail(c, ECMD_EINVAL, "max_nodes must be >= 0");
+    if (s->frontier_batch < 0 || s->frontier_batch > 1024)
+        return fail(c, ECMD_EINVAL, "frontier_batch must be in [0, 1024]");
+    if (s->frontier_capacity < 0) return fail(c, ECMD_EINVAL, "frontier_capacity must be >= 0");
+    return ECMD_OK;
+}
+
+// Event arrays of a call: device pointers (borrowed) or staged copies.
+struct Inputs {
+    const float *x = nullptr, *y = nullptr, *t = nullptr, *seeds = nullptr, *tau = nullptr;
+    const long long* off = nullptr;
+};
+
+static int stage(ecmd_ctx* c, DevBuf& buf, const void* src, size_t bytes, uint32_t flags,
+                 const void** out) {
+    if (flags & ECMD_DEVICE_PTR) {
+        *out = src;
+        return ECMD_OK;
+    }
+    HIPCHK(c, buf.ensure(bytes));
+    if (bytes) HIPCHK(c, hipMemcpyAsync(buf.p, src, bytes, hipMemcpyHostToDevice, c->stream));
+    *out = buf.p;
+    return ECMD_OK;
+}
+
+static double key_to_double(long long hi, unsigned long long lo) {
+    __int128 k = (__int128)(((unsigned __int128)(unsigned long long)hi << 64) | (unsigned __int128)lo);
+    return (double)k;
+}
+
+// --------------------------------------------------------------- pipeline
+
+// Prep of B windows: window params, event binning.  Needs h_off (host copy
+// of the offsets) and h_tau.
+static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, float d_lo, float d_hi,
+                    int* nblk_out) {
+    const int T = g.T;
+    std::vector<int> blk(B + 1, 0);
+    for (int w = 0; w < B; ++w) {
+        long long n = c->h_off[w + 1] - c->h_off[w];
+        blk[w + 1] = blk[w] + (int)((n + kChunk - 1) / kChunk);
+    }
+    const int nblk = blk[B];
+    HIPCHK(c, c->wp.ensure(sizeof(WinParam) * std::max(B, 1)));
+    HIPCHK(c, c->blk.ensure(sizeof(int) * (B + 1)));
+    HIPCHK(c, c->pinned.ensure(sizeof(int) * (B + 1) + 64));
+    memcpy(c->pinned.p, blk.data(), sizeof(int) * (B + 1));
+    HIPCHK(c, hipMemcpyAsync(c->blk.p, c->pinned.p, sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, c->cnt_own.ensure(sizeof(int) * B * T));
+    HIPCHK(c, c->cnt_guest.ensure(sizeof(int) * B * T));
+    HIPCHK(c, c->seg_off.ensure(sizeof(long long) * (B * T + 1)));
+    HIPCHK(c, c->seg_own.ensure(sizeof(int) * B * T));
+    HIPCHK(c, c->cursor.ensure(sizeof(unsigned long long) * 2 * B * T));
+    HIPCHK(c, c->err_flag.ensure(sizeof(int)));
+    HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * B * T, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cnt_guest.p, 0, sizeof(int) * B * T, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
+    HIPCHK(c, launch_winparam(c->stream, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
+    // count + scan (scatter needs the total to size the event store)
+    HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
+                          nblk, kChunk, c->cnt_own.as<int>(), c->cnt_guest.as<int>(), c->seg_off.as<long long>(),
+                          c->seg_own.as<int>(), c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>()));
+    HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char*)c->pinned.p + 8, c->err_flag.p, sizeof(int), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const long long total = *(long long*)c->pinned.p;
+    const int errf = *(int*)((char*)c->pinned.p + 8);
+    if (errf)
+        return fail(c, ECMD_EINVAL, "an event has a non-finite coordinate or t_rel outside [0, tau]");
+    HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)std::max(total, 1ll)));
+    HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
+                          nblk, kChunk, nullptr, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
+                          c->ev.as<float4>(), nullptr));
+    *nblk_out = nblk;
+    return ECMD_OK;
+}
+
+static int eval_blocks(ecmd_ctx* c, size_t lds) {
+    int per_cu = 0;
+    if (eval_occupancy(&per_cu, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    return c->num_cu * std::min(per_cu, 4);
+}
+
+// Whole batched search on staged inputs; fills out[0..B).
+static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, int B,
+                      const ecmd_search* search, int L, ecmd_result* out) {
+    const int W = sensor->width, H = sensor->height;
+    const long long M = (long long)W * H;
+    const int max_px = (int)((c->max_lds - 1024) / sizeof(unsigned));
+    Geometry g;
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, max_px, g))
+        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles);
+    int nblk = 0;
+    int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk);
+    if (rc) return rc;
+
+    Search sp;
+    sp.d_lo = search->d_lo;
+    sp.d_hi = search->d_hi;
+    sp.L = L;
+    sp.F = search->frontier_batch > 0 ? search->frontier_batch : kDefaultF;
+    sp.CAP = search->frontier_capacity > 0 ? search->frontier_capacity : kDefaultCap;
+    sp.HS = 3 * sp.F;
+    sp.max_nodes = search->max_nodes;
+    sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
+    sp.M = M;
+    const int T = g.T;
+    HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
+    HIPCHK(c, c->front.ensure(sizeof(Node) * (size_t)B * sp.CAP));
+    HIPCHK(c, c->sel.ensure(sizeof(Sel) * (size_t)B * sp.F));
+    HIPCHK(c, c->hyps.ensure(sizeof(Hyp) * (size_t)B * sp.HS));
+    HIPCHK(c, c->items.ensure(sizeof(Item) * (size_t)B * sp.HS * T));
+    HIPCHK(c, c->queues.ensure(sizeof(Queue) * 2));
+    HIPCHK(c, c->part.ensure(sizeof(Part) * (size_t)B * sp.HS * T));
+    HIPCHK(c, c->n_active.ensure(sizeof(int)));
+    HIPCHK(c, hipMemsetAsync(c->queues.p, 0, sizeof(Queue) * 2, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->n_active.p, 0, sizeof(int), c->stream));
+    Queue* q = c->queues.as<Queue>();
+    HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
+                          c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[0], T,
+                          c->seg_off.as<long long>()));
+    const size_t lds = (size_t)g.max_tile_px * sizeof(unsigned);
+    HIPCHK(c, eval_set_lds(lds));
+    const int nb = eval_blocks(c, lds);
+    int parity = 0;
+    int* h_active = (int*)c->pinned.p;
+    int active = B;
+    for (int step = 0; step < kMaxSteps && active > 0; ++step) {
+        HIPCHK(c, launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+                              c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[parity],
+                              &q[1 - parity], c->part.as<Part>(), sp.HS, nullptr));
+        HIPCHK(c, launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
+                                  c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(),
+                                  c->hyps.as<Hyp>(), c->part.as<Part>(), c->items.as<Item>(),
+                                  &q[1 - parity], c->n_active.as<int>()));
+        parity = 1 - parity;
+        if ((step & 3) == 3) {
+            HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            active = B + *h_active;  // n_active counts finished windows down from zero
+        }
+    }
+    std::vector<WinState> hs(B);
+    HIPCHK(c, hipMemcpyAsync(hs.data(), c->state.p, sizeof(WinState) * B, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int first_status = ECMD_OK;
+    for (int w = 0; w < B; ++w) {
+        const WinState& s = hs[w];
+        ecmd_result& r = out[w];
+        memset(&r, 0, sizeof r);
+        r.status = s.active ? ECMD_EBUDGET : s.status;
+        r.j_star = s.j_inc;
+        r.L = (uint32_t)L;
+        r.d_hat = host_grid_d(search->d_lo, search->d_hi, L, s.j_inc);
+        r.K_lo = s.Kinc_lo;
+        r.K_hi = s.Kinc_hi;
+        const double M2 = (double)M * (double)M;
+        r.contrast = key_to_double(s.Kinc_hi, s.Kinc_lo) / M2;
+        const double tau = (double)c->h_tau[w];
+        r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * tau);
+        if (s.status == ECMD_EFRONTIER) r.gap = INFINITY;
+        else r.gap = key_to_double(s.gap_hi, s.gap_lo) / M2;
+        r.n_events = c->h_off[w + 1] - c->h_off[w];
+        r.nodes_expanded = s.nodes_expanded;
+        r.nodes_pruned = s.nodes_pruned;
+        r.point_evals = s.point_evals;
+        r.bound_evals = s.bound_evals;
+        r.event_hyp_evals = s.event_hyp;
+        r.pixel_updates = s.pixel_updates;
+        r.steps = s.steps;
+        r.seeded = s.seeded;
+        if (r.status != ECMD_OK && first_status == ECMD_OK) first_status = r.status;
+    }
+    return first_status;
+}
+
+static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y,
+                        const float* t_rel, const int64_t* offsets, const float* tau, int32_t B,
+                        const ecmd_search* search, uint32_t flags, const float* d_seeds, ecmd_result* out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    int L = 0;
+    rc = check_search(c, search, &L);
+    if (rc) return rc;
+    if (B < 0 || B > 65535) return fail(c, ECMD_EINVAL, "B = %d out of range", B);
+    if (B == 0) return ECMD_OK;
+    if (!offsets || !tau || !out) return fail(c, ECMD_EINVAL, "NULL offsets, tau or out");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->h_off.assign(B + 1, 0);
+    c->h_tau.assign(B, 0.0f);
+    if (flags & ECMD_DEVICE_PTR) {
+        HIPCHK(c, hipMemcpyAsync(c->h_off.data(), offsets, sizeof(long long) * (B + 1), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->h_tau.data(), tau, sizeof(float) * B, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        memcpy(c->h_off.data(), offsets, sizeof(long long) * (B + 1));
+        memcpy(c->h_tau.data(), tau, sizeof(float) * B);
+    }
+    if (c->h_off[0] < 0) return fail(c, ECMD_EINVAL, "offsets[0] < 0");
+    for (int w = 0; w < B; ++w) {
+        long long n = c->h_off[w + 1] - c->h_off[w];
+        if (n < 0) return fail(c, ECMD_EINVAL, "offsets decrease at window %d", w);
+        if (n > (1ll << 31) - 1) return fail(c, ECMD_EINVAL, "window %d has too many events", w);
+        double bound = (double)n * (double)n * 2.0 * ((double)sensor->width + sensor->height + 3.0);
+        if (bound >= 9.0e18) return fail(c, ECMD_EINVAL, "window %d: sums would overflow 64 bits", w);
+        float t = c->h_tau[w];
+        if (!(t > 0.0f) || !isfinite(t)) return fail(c, ECMD_EINVAL, "tau[%d] must be > 0", w);
+        if (!(search->d_hi * t < 1.0f))
+            return fail(c, ECMD_EINVAL, "window %d: d_hi * tau must be < 1 (cheirality)", w);
+    }
+    const long long n_total = c->h_off[B];
+    if (n_total > 0 && (!x || !y || !t_rel)) return fail(c, ECMD_EINVAL, "NULL event arrays");
+    Inputs in;
+    const void* p;
+    if ((rc = stage(c, c->sx, x, sizeof(float) * n_total, flags, &p))) return rc;
+    in.x = (const float*)p;
+    if ((rc = stage(c, c->sy, y, sizeof(float) * n_total, flags, &p))) return rc;
+    in.y = (const float*)p;
+    if ((rc = stage(c, c->st, t_rel, sizeof(float) * n_total, flags, &p))) return rc;
+    in.t = (const float*)p;
+    if ((rc = stage(c, c->soff, offsets, sizeof(long long) * (B + 1), flags, &p))) return rc;
+    in.off = (const long long*)p;
+    if ((rc = stage(c, c->stau, tau, sizeof(float) * B, flags, &p))) return rc;
+    in.tau = (const float*)p;
+    if (d_seeds) {
+        if ((rc = stage(c, c->sseed, d_seeds, sizeof(float) * B, flags, &p))) return rc;
+        in.seeds = (const float*)p;
+    }
+    return run_search(c, sensor, in, B, search, L, out);
+}
+
+// ------------------------------------------------------------------ ABI
+
+extern "C" {
+
+const char* ecmd_version(void) { return "ecmd-mi355x 0.1"; }
+
+int ecmd_ctx_create(ecmd_ctx** out, int device, void* hip_stream) {
+    if (!out) return ECMD_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return ECMD_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return ECMD_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return ECMD_EDEVICE;
+    ecmd_ctx* c = new (std::nothrow) ecmd_ctx();
+    if (!c) return ECMD_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->num_cu = prop.multiProcessorCount;
+    c->max_lds = prop.sharedMemPerBlock;
+    *out = c;
+    return ECMD_OK;
+}
+
+void ecmd_ctx_destroy(ecmd_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf* bufs[] = {&c->sx, &c->sy, &c->st, &c->soff, &c->stau, &c->sseed, &c->wp, &c->blk, &c->cnt_own,
+                      &c->cnt_guest, &c->seg_off, &c->seg_own, &c->cursor, &c->ev, &c->err_flag, &c->state,
+                      &c->front, &c->sel, &c->hyps, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
+                      &c->img, &c->keep, &c->counts, &c->misc};
+    for (DevBuf* b : bufs) b->release();
+    c->pinned.release();
+    delete c;
+}
+
+const char* ecmd_last_error(const ecmd_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int ecmd_estimate_divergence_batched(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y,
+                                     const float* t_rel, const int64_t* offsets, const float* tau, int32_t B,
+                                     const ecmd_search* search, uint32_t flags, const float* d_seeds,
+                                     ecmd_result* out) {
+    return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, d_seeds, out);
+}
+
+int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_events* events,
+                             ecmd_window window, const ecmd_search* search, uint32_t flags, const float* d_seed,
+                             ecmd_result* out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    if (!events || !out) return fail(c, ECMD_EINVAL, "NULL events or out");
+    if (events->n < 0) return fail(c, ECMD_EINVAL, "n < 0");
+    if (!isfinite(window.t0) || !isfinite(window.t1) || !(window.t1 > window.t0))
+        return fail(c, ECMD_EINVAL, "window must have t0 < t1");
+    const float tau = (float)(window.t1 - window.t0);
+    const long long n = events->n;
+    if (n > 0 && (!events->x || !events->y || !events->t)) return fail(c, ECMD_EINVAL, "NULL event arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    long long m = 0;
+    float* dx;
+    float* dy;
+    float* dt;
+    if (flags & ECMD_DEVICE_PTR) {
+        HIPCHK(c, c->sx.ensure(sizeof(float) * std::max(n, 1ll)));
+        HIPCHK(c, c->sy.ensure(sizeof(float) * std::max(n, 1ll)));
+        HIPCHK(c, c->st.ensure(sizeof(float) * std::max(n, 1ll)));
+        const int nb = (int)((n + 1023) / 1024);
+        HIPCHK(c, c->keep.ensure(sizeof(int) * (nb + 1)));
+        HIPCHK(c, c->misc.ensure(sizeof(long long)));
+        HIPCHK(c, c->err_flag.ensure(sizeof(int)));
+        HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
+        HIPCHK(c, launch_select(c->stream, events->x, events->y, events->t, n, window.t0, window.t1, c->sx.as<float>(),
+                                c->sy.as<float>(), c->st.as<float>(), c->keep.as<int>(), c->misc.as<long long>()));
+        HIPCHK(c, c->pinned.ensure(64));
+        HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->misc.p, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        m = *(long long*)c->pinned.p;
+        dx = c->sx.as<float>();
+        dy = c->sy.as<float>();
+        dt = c->st.as<float>();
+    } else {
+        std::vector<float> hx, hy, ht;
+        hx.reserve(n);
+        for (long long i = 0; i < n; ++i) {
+            double t = events->t[i];
+            if (t >= window.t0 && t <= window.t1) {
+                hx.push_back(events->x[i]);
+                hy.push_back(events->y[i]);
+                ht.push_back((float)(t - window.t0));
+            }
+        }
+        m = (long long)hx.size();
+        HIPCHK(c, c->sx.ensure(sizeof(float) * std::max(m, 1ll)));
+        HIPCHK(c, c->sy.ensure(sizeof(float) * std::max(m, 1ll)));
+        HIPCHK(c, c->st.ensure(sizeof(float) * std::max(m, 1ll)));
+        if (m) {
+            HIPCHK(c, hipMemcpyAsync(c->sx.p, hx.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->sy.p, hy.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->st.p, ht.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+        }
+        HIPCHK(c, hipStreamSynchronize(c->stream));  // host vectors die at scope end
+        dx = c->sx.as<float>();
+        dy = c->sy.as<float>();
+        dt = c->st.as<float>();
+    }
+    long long off[2] = {0, m};
+    float seed = d_seed ? *d_seed : NAN;
+    // the staged arrays are device memory: run the batched path on them
+    int rc;
+    {
+        // offsets, tau and the seed are tiny: pass them as host values
+        int L = 0;
+        rc = check_sensor(c, sensor);
+        if (rc) return rc;
+        rc = check_search(c, search, &L);
+        if (rc) return rc;
+        c->h_off.assign(off, off + 2);
+        c->h_tau.assign(1, tau);
+        if (!(tau > 0.0f)) return fail(c, ECMD_EINVAL, "window too short");
+        if (!(search->d_hi * tau < 1.0f)) return fail(c, ECMD_EINVAL, "d_hi * tau must be < 1 (cheirality)");
+        double bound = (double)m * (double)m * 2.0 * ((double)sensor->width + sensor->height + 3.0);
+        if (bound >= 9.0e18 || m > (1ll << 31) - 1) return fail(c, ECMD_EINVAL, "window has too many events");
+        Inputs in;
+        in.x = dx;
+        in.y = dy;
+        in.t = dt;
+        const void* p;
+        if ((rc = stage(c, c->soff, off, sizeof off, 0, &p))) return rc;
+        in.off = (const long long*)p;
+        if ((rc = stage(c, c->stau, &tau, sizeof tau, 0, &p))) return rc;
+        in.tau = (const float*)p;
+        if (d_seed) {
+            if ((rc = stage(c, c->sseed, &seed, sizeof seed, 0, &p))) return rc;
+            in.seeds = (const float*)p;
+        }
+        rc = run_search(c, sensor, in, 1, search, L, out);
+    }
+    return rc;
+}
+
+int ecmd_probe_pixels(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                      int64_t n, float tau, float d, uint32_t flags, int32_t* pix_out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    if (n < 0 || !(tau > 0.0f) || !isfinite(d) || (n > 0 && (!x || !y || !t_rel || !pix_out)))
+        return fail(c, ECMD_EINVAL, "bad probe arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const void *px, *py, *pt;
+    if ((rc = stage(c, c->sx, x, sizeof(float) * n, flags, &px))) return rc;
+    if ((rc = stage(c, c->sy, y, sizeof(float) * n, flags, &py))) return rc;
+    if ((rc = stage(c, c->st, t_rel, sizeof(float) * n, flags, &pt))) return rc;
+    int* dpix = (int*)pix_out;
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->pix.ensure(sizeof(int) * std::max(n, (int64_t)1)));
+        dpix = c->pix.as<int>();
+    }
+    HIPCHK(c, launch_probe_pixels(c->stream, (const float*)px, (const float*)py, (const float*)pt, n, tau, d,
+                                  sensor->width, sensor->height, sensor->foe_x, sensor->foe_y, dpix));
+    if (!(flags & ECMD_DEVICE_PTR) && n)
+        HIPCHK(c, hipMemcpyAsync(pix_out, dpix, sizeof(int) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+// Evaluate m hypotheses (points if d_b == NULL) on one window.
+static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                      int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
+                      uint32_t flags, uint64_t* S, int64_t* N, uint32_t* img_out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    if (n < 0 || m < 0 || !(tau > 0.0f) || (n > 0 && (!x || !y || !t_rel)) || (m > 0 && (!d_a || !S || !N)))
+        return fail(c, ECMD_EINVAL, "bad probe arguments");
+    if (m == 0) return ECMD_OK;
+    if (!(d_lo >= 0.0f) || !(d_lo <= d_hi) || !(d_hi * tau < 1.0f))
+        return fail(c, ECMD_EINVAL, "probe range must satisfy 0 <= d_lo <= d_hi, d_hi * tau < 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int W = sensor->width, H = sensor->height;
+    const long long M = (long long)W * H;
+    const int max_px = (int)((c->max_lds - 1024) / sizeof(unsigned));
+    Geometry g;
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, max_px, g))
+        return fail(c, ECMD_EINVAL, "sensor needs more than %d tiles", kMaxTiles);
+    const int T = g.T;
+    Inputs in;
+    const void* p;
+    if ((rc = stage(c, c->sx, x, sizeof(float) * n, flags, &p))) return rc;
+    in.x = (const float*)p;
+    if ((rc = stage(c, c->sy, y, sizeof(float) * n, flags, &p))) return rc;
+    in.y = (const float*)p;
+    if ((rc = stage(c, c->st, t_rel, sizeof(float) * n, flags, &p))) return rc;
+    in.t = (const float*)p;
+    long long off[2] = {0, n};
+    if ((rc = stage(c, c->soff, off, sizeof off, 0, &p))) return rc;
+    in.off = (const long long*)p;
+    if ((rc = stage(c, c->stau, &tau, sizeof tau, 0, &p))) return rc;
+    in.tau = (const float*)p;
+    c->h_off.assign(off, off + 2);
+    c->h_tau.assign(1, tau);
+    int nblk = 0;
+    rc = run_prep(c, g, in, 1, d_lo, d_hi, &nblk);
+    if (rc) return rc;
+    const void *pa, *pb = nullptr;
+    if ((rc = stage(c, c->sseed, d_a, sizeof(float) * m, flags, &pa))) return rc;
+    if (d_b) {
+        if ((rc = stage(c, c->misc, d_b, sizeof(float) * m, flags, &pb))) return rc;
+    }
+    HIPCHK(c, c->hyps.ensure(sizeof(Hyp) * m));
+    HIPCHK(c, launch_rates(c->stream, (const float*)pa, (const float*)pb, m, tau, c->hyps.as<Hyp>()));
+    // every hypothesis on every tile
+    std::vector<Item> items((size_t)m * T);
+    for (int h = 0; h < m; ++h)
+        for (int t = 0; t < T; ++t) items[(size_t)h * T + t] = Item{h, t};
+    HIPCHK(c, c->items.ensure(sizeof(Item) * items.size()));
+    HIPCHK(c, hipMemcpyAsync(c->items.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    Queue hq[2] = {{(int)items.size(), 0}, {0, 0}};
+    HIPCHK(c, c->queues.ensure(sizeof hq));
+    HIPCHK(c, hipMemcpyAsync(c->queues.p, hq, sizeof hq, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, c->part.ensure(sizeof(Part) * items.size()));
+    unsigned* dimg = nullptr;
+    if (img_out) {
+        if (flags & ECMD_DEVICE_PTR) {
+            dimg = img_out;
+        } else {
+            HIPCHK(c, c->img.ensure(sizeof(unsigned) * (size_t)m * M));
+            dimg = c->img.as<unsigned>();
+        }
+    }
+    const size_t lds = (size_t)g.max_tile_px * sizeof(unsigned);
+    HIPCHK(c, eval_set_lds(lds));
+    Queue* q = c->queues.as<Queue>();
+    HIPCHK(c, launch_eval(c->stream, g, eval_blocks(c, lds), lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[0], &q[1],
+                          c->part.as<Part>(), m, dimg));
+    std::vector<Part> parts(items.size());
+    std::vector<long long> seg(T + 1);
+    HIPCHK(c, hipMemcpyAsync(parts.data(), c->part.p, sizeof(Part) * parts.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(seg.data(), c->seg_off.p, sizeof(long long) * (T + 1), hipMemcpyDeviceToHost,
+                             c->stream));
+    if (img_out && !(flags & ECMD_DEVICE_PTR))
+        HIPCHK(c, hipMemcpyAsync(img_out, dimg, sizeof(unsigned) * (size_t)m * M, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<uint64_t> hS(m, 0);
+    std::vector<int64_t> hN(m, 0);
+    for (int h = 0; h < m; ++h) {
+        for (int t = 0; t < T; ++t) {
+            if (seg[t + 1] == seg[t]) continue;  // empty tile: not evaluated, contributes 0
+            hS[h] += parts[(size_t)h * T + t].S;
+            hN[h] += parts[(size_t)h * T + t].N;
+        }
+    }
+    if (flags & ECMD_DEVICE_PTR) {
+        HIPCHK(c, hipMemcpyAsync(S, hS.data(), sizeof(uint64_t) * m, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(N, hN.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        memcpy(S, hS.data(), sizeof(uint64_t) * m);
+        memcpy(N, hN.data(), sizeof(int64_t) * m);
+    }
+    return ECMD_OK;
+}
+
+int ecmd_probe_point(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                     int64_t n, float tau, const float* d, int32_t m, uint32_t flags, uint64_t* S, int64_t* N,
+                     uint32_t* img_out) {
+    if (!c) return ECMD_EINVAL;
+    if (m < 0 || (m > 0 && !d)) return fail(c, ECMD_EINVAL, "bad probe arguments");
+    // binning range: the span of the probed divergences
+    std::vector<float> hd(m);
+    if (m) {
+        if (flags & ECMD_DEVICE_PTR) {
+            HIPCHK(c, hipMemcpy(hd.data(), d, sizeof(float) * m, hipMemcpyDeviceToHost));
+        } else {
+            memcpy(hd.data(), d, sizeof(float) * m);
+        }
+    }
+    float lo = INFINITY, hi = -INFINITY;
+    for (float v : hd) {
+        if (!isfinite(v)) return fail(c, ECMD_EINVAL, "non-finite divergence");
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+    }
+    if (m == 0) lo = hi = 0.0f;
+    return probe_impl(c, sensor, x, y, t_rel, n, tau, lo, hi, d, nullptr, m, flags, S, N, img_out);
+}
+
+int ecmd_probe_bound(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                     int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
+                     uint32_t flags, uint64_t* S_bar, int64_t* N_low, uint32_t* img_out) {
+    if (!c) return ECMD_EINVAL;
+    if (m > 0 && (!d_a || !d_b)) return fail(c, ECMD_EINVAL, "NULL interval ends");
+    std::vector<float> ha(m), hb(m);
+    if (m) {
+        if (flags & ECMD_DEVICE_PTR) {
+            HIPCHK(c, hipMemcpy(ha.data(), d_a, sizeof(float) * m, hipMemcpyDeviceToHost));
+            HIPCHK(c, hipMemcpy(hb.data(), d_b, sizeof(float) * m, hipMemcpyDeviceToHost));
+        } else {
+            memcpy(ha.data(), d_a, sizeof(float) * m);
+            memcpy(hb.data(), d_b, sizeof(float) * m);
+        }
+    }
+    for (int k = 0; k < m; ++k)
+        if (!(ha[k] >= d_lo && ha[k] <= hb[k] && hb[k] <= d_hi))
+            return fail(c, ECMD_EINVAL, "interval %d not inside [d_lo, d_hi] or reversed", k);
+    return probe_impl(c, sensor, x, y, t_rel, n, tau, d_lo, d_hi, d_a, d_b, m, flags, S_bar, N_low, img_out);
+}
+
+int ecmd_downsample(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const int64_t* offsets,
+                    int32_t B, uint32_t flags, uint16_t* out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    if (B < 0 || !offsets || !out) return fail(c, ECMD_EINVAL, "bad downsample arguments");
+    if (B == 0) return ECMD_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<long long> off(B + 1);
+    if (flags & ECMD_DEVICE_PTR) {
+        HIPCHK(c, hipMemcpy(off.data(), offsets, sizeof(long long) * (B + 1), hipMemcpyDeviceToHost));
+    } else {
+        memcpy(off.data(), offsets, sizeof(long long) * (B + 1));
+    }
+    std::vector<int> blk(B + 1, 0);
+    for (int w = 0; w < B; ++w) {
+        long long n = off[w + 1] - off[w];
+        if (n < 0 || off[0] < 0) return fail(c, ECMD_EINVAL, "offsets must be non-decreasing and >= 0");
+        blk[w + 1] = blk[w] + (int)((n + kChunk - 1) / kChunk);
+    }
+    const long long n_total = off[B];
+    if (n_total > 0 && (!x || !y)) return fail(c, ECMD_EINVAL, "NULL event arrays");
+    const void *px, *py, *po;
+    if ((rc = stage(c, c->sx, x, sizeof(float) * n_total, flags, &px))) return rc;
+    if ((rc = stage(c, c->sy, y, sizeof(float) * n_total, flags, &py))) return rc;
+    if ((rc = stage(c, c->soff, offsets, sizeof(long long) * (B + 1), flags, &po))) return rc;
+    HIPCHK(c, c->blk.ensure(sizeof(int) * (B + 1)));
+    HIPCHK(c, hipMemcpyAsync(c->blk.p, blk.data(), sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, c->counts.ensure(sizeof(unsigned) * (size_t)B * 4096));
+    HIPCHK(c, hipMemsetAsync(c->counts.p, 0, sizeof(unsigned) * (size_t)B * 4096, c->stream));
+    uint16_t* dout = out;
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->img.ensure(sizeof(uint16_t) * (size_t)B * 4096));
+        dout = c->img.as<uint16_t>();
+    }
+    HIPCHK(c, launch_downsample(c->stream, (const float*)px, (const float*)py, (const long long*)po, B,
+                                sensor->width, sensor->height, c->blk.as<int>(), blk[B], kChunk,
+                                c->counts.as<unsigned>(), dout));
+    if (!(flags & ECMD_DEVICE_PTR))
+        HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(uint16_t) * (size_t)B * 4096, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+}  // extern "C"

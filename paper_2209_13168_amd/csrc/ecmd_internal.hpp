@@ -1,0 +1,145 @@
+// Internal types and launchers of the MI355X divergence estimator.
+//
+// Layout in HBM (per batch of B windows sharing one sensor):
+//   * events are binned by image tile: segment (w, t) holds the events of
+//     window w whose root trajectory (all d in [d_lo, d_hi]) can reach tile
+//     t, as float4 (x, y, ax, ay); the events owned by the tile come first
+//     (they count towards N_low), guest copies after.  With an integer FOE
+//     inside the sensor the tiles split the image at the FOE lines, which no
+//     event ever crosses (the warp of eq. (12) only moves events away from
+//     the FOE), so there are no guests unless a quadrant is itself split;
+//   * hypotheses: per window HS = 3F slots (F centre points, then two child
+//     intervals per expanded node), as rates r = d / (1 - d tau);
+//   * partial sums per (window, slot, tile), summed by the frontier step;
+//   * frontier: up to CAP nodes per window, key K_bar as a signed 128-bit
+//     integer, and the incumbent (K, j) per window.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecmd {
+
+typedef __int128 i128;
+
+constexpr int kMaxTiles = 64;    // tiles per sensor
+constexpr int kEvalThreads = 512;  // threads of an evaluation workgroup
+constexpr int kFrontThreads = 256;  // threads of a frontier workgroup
+
+enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2 };
+
+struct Hyp {
+    float ra, rb;  // rates of the interval ends (equal for a point)
+    int kind;
+    int pad;
+};
+
+struct Part {
+    unsigned long long S;  // sum of squared counts over the tile
+    long long N;           // in-image events (point) or N_low (interval)
+    unsigned long long U;  // pixel increments
+    long long pad;
+};
+
+struct Node {
+    unsigned long long klo;  // key K_bar, low and high 64-bit words
+    long long khi;
+    unsigned ja, jb;  // grid interval [ja, jb]
+};
+
+struct Sel {
+    unsigned ja, jb, jc, kids;  // expanded node, its centre, 1 if it has children
+};
+
+struct Geometry {
+    int W, H;
+    float cx, cy;
+    int T;                        // number of tiles
+    int ntx, nty;                 // tile grid
+    int colcut[kMaxTiles + 1];    // column band edges (ntx + 1)
+    int rowcut[kMaxTiles + 1];    // row band edges (nty + 1)
+    int max_tile_px;              // largest tile area (pixels)
+};
+
+struct WinParam {
+    float tau;
+    float r_lo, r_hi;  // rates at d_lo and d_hi
+    int pad;
+    long long n_events;
+};
+
+struct Search {
+    float d_lo, d_hi;
+    int L;
+    int F;    // nodes expanded together per step
+    int CAP;  // frontier capacity per window
+    int HS;   // hypothesis slots per window (3F)
+    long long max_nodes;
+    long long gamma_key;  // stop when best K_bar - K_inc <= gamma_key (-1: gamma = 0)
+    long long M;          // pixels
+};
+
+struct WinState {
+    unsigned long long Kinc_lo;
+    long long Kinc_hi;
+    unsigned long long gap_lo;  // certified gap key at stop (budget / gamma)
+    long long gap_hi;
+    unsigned j_inc;
+    int status;
+    int active;
+    int n_front;
+    int n_sel;
+    int steps;
+    int seeded;
+    int pad;
+    long long nodes_expanded, nodes_pruned, point_evals, bound_evals;
+    long long event_hyp, pixel_updates;
+};
+
+struct Item {
+    int wh;  // window * HS + slot
+    int t;   // tile
+};
+
+struct Queue {
+    int n_items;
+    int next;
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `s` and return the launch status.
+
+hipError_t launch_winparam(hipStream_t s, const float* tau, const long long* offsets, int B,
+                           float d_lo, float d_hi, WinParam* wp);
+// phase 0: count events per (window, tile) and scan into segments;
+// phase 1: scatter the events into their segments.
+hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
+                       const float* t_rel, const long long* offsets, const WinParam* wp, int B,
+                       const int* blk_start, int nblk, int chunk, int* cnt_own, int* cnt_guest,
+                       long long* seg_off, int* seg_own, unsigned long long* cursor, float4* ev,
+                       int* err_flag);
+hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
+                       WinState* st, Sel* sel, Hyp* hyps, Item* items, Queue* q, int T,
+                       const long long* seg_off);
+hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
+                           const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
+                           const Part* part, Item* items, Queue* q_fill, int* n_active);
+hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes,
+                       const float4* ev, const long long* seg_off, const int* seg_own,
+                       const Hyp* hyps, const Item* items, Queue* q, Queue* q_reset, Part* part,
+                       int HS, unsigned* img_out);
+hipError_t launch_rates(hipStream_t s, const float* d_a, const float* d_b, int m, float tau, Hyp* hyps);
+hipError_t launch_probe_pixels(hipStream_t s, const float* x, const float* y, const float* t_rel,
+                               long long n, float tau, float d, int W, int H, float cx, float cy,
+                               int* pix);
+hipError_t launch_downsample(hipStream_t s, const float* x, const float* y, const long long* offsets,
+                             int B, int W, int H, const int* blk_start, int nblk, int chunk,
+                             unsigned* counts, uint16_t* out);
+hipError_t eval_set_lds(size_t bytes);
+hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes);
+// Events with t in [t0, t1], compacted in order, t_rel = float(t - t0).
+hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, long long n,
+                         double t0, double t1, float* xo, float* yo, float* to, int* blk_cnt,
+                         long long* total);
+
+}  // namespace ecmd

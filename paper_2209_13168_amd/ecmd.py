@@ -1,0 +1,324 @@
+"""Thin Python binding of ``libecmd.so`` (argument marshalling only).
+
+Every step of the estimator runs in the library's HIP kernels; this module
+only converts arrays to pointers.  Arrays may be NumPy (host memory) or
+torch tensors on the context's GPU (device memory, ``ECMD_DEVICE_PTR``); a
+call uses one kind for all its arrays.  The library must have been built
+(``paper_2209_13168_amd/build.py``); importing fails loudly otherwise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, fields
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_build", "libecmd.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EFRONTIER = 0, -1, -2, -3, -4, -5
+DEVICE_PTR = 1
+CNN_NPARAM = 23361
+GRID = 64
+
+
+class EcmdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ecmd error {code}: {msg}")
+        self.code = code
+
+
+class Sensor(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("foe_x", C.c_float), ("foe_y", C.c_float)]
+
+
+class EventsS(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("t", C.c_void_p), ("n", C.c_int64)]
+
+
+class WindowS(C.Structure):
+    _fields_ = [("t0", C.c_double), ("t1", C.c_double)]
+
+
+class SearchS(C.Structure):
+    _fields_ = [("d_lo", C.c_float), ("d_hi", C.c_float), ("eps", C.c_float), ("reserved0", C.c_float),
+                ("gamma", C.c_double), ("max_nodes", C.c_int64), ("frontier_batch", C.c_int32),
+                ("frontier_capacity", C.c_int32)]
+
+
+class ResultS(C.Structure):
+    _fields_ = [("status", C.c_int32), ("j_star", C.c_uint32), ("L", C.c_uint32), ("d_hat", C.c_float),
+                ("contrast", C.c_double), ("d_end", C.c_double), ("gap", C.c_double),
+                ("K_lo", C.c_uint64), ("K_hi", C.c_int64), ("n_events", C.c_int64),
+                ("nodes_expanded", C.c_int64), ("nodes_pruned", C.c_int64), ("point_evals", C.c_int64),
+                ("bound_evals", C.c_int64), ("event_hyp_evals", C.c_int64), ("pixel_updates", C.c_int64),
+                ("steps", C.c_int32), ("seeded", C.c_int32)]
+
+
+@dataclass
+class Result:
+    status: int
+    j_star: int
+    L: int
+    d_hat: float
+    K: int
+    contrast: float
+    d_end: float
+    gap: float
+    n_events: int
+    nodes_expanded: int
+    nodes_pruned: int
+    point_evals: int
+    bound_evals: int
+    event_hyp_evals: int
+    pixel_updates: int
+    steps: int
+    seeded: int
+
+    @classmethod
+    def of(cls, r: ResultS) -> "Result":
+        K = (int(r.K_hi) << 64) | int(r.K_lo)
+        vals = {f.name: getattr(r, f.name) for f in fields(cls) if f.name != "K"}
+        return cls(K=K, **vals)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_float
+    sig = {
+        "ecmd_version": ([], C.c_char_p),
+        "ecmd_ctx_create": ([C.POINTER(vp), C.c_int, vp], C.c_int),
+        "ecmd_ctx_destroy": ([vp], None),
+        "ecmd_last_error": ([vp], C.c_char_p),
+        "ecmd_estimate_divergence": ([vp, C.POINTER(Sensor), C.POINTER(EventsS), WindowS,
+                                      C.POINTER(SearchS), u32, vp, C.POINTER(ResultS)], C.c_int),
+        "ecmd_estimate_divergence_batched": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32,
+                                              C.POINTER(SearchS), u32, vp, C.POINTER(ResultS)], C.c_int),
+        "ecmd_probe_pixels": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, f32, u32, vp], C.c_int),
+        "ecmd_probe_point": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, vp, i32, u32, vp, vp, vp],
+                             C.c_int),
+        "ecmd_probe_bound": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, f32, f32, vp, vp, i32, u32,
+                              vp, vp, vp], C.c_int),
+        "ecmd_downsample": ([vp, C.POINTER(Sensor), vp, vp, vp, i32, u32, vp], C.c_int),
+        "ecmd_cnn_create": ([vp, C.c_uint64, C.POINTER(vp)], C.c_int),
+        "ecmd_cnn_destroy": ([vp], None),
+        "ecmd_cnn_get_params": ([vp, vp], C.c_int),
+        "ecmd_cnn_set_params": ([vp, vp], C.c_int),
+        "ecmd_cnn_forward": ([vp, vp, i32, u32, vp], C.c_int),
+        "ecmd_cnn_grads": ([vp, vp, vp, i32, u32, vp, vp], C.c_int),
+        "ecmd_cnn_train_step": ([vp, vp, vp, i32, f32, u32, vp], C.c_int),
+        "ecmd_estimate_divergence_learned": ([vp, vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32,
+                                              C.POINTER(SearchS), u32, C.POINTER(ResultS)], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class _Args:
+    """Pointer marshalling for one call: all arrays host (NumPy) or all
+    device (torch CUDA tensors)."""
+
+    def __init__(self):
+        self.keep = []
+        self.device = None
+
+    def ptr(self, a, dtype):
+        if a is None:
+            return None
+        if _is_torch(a):
+            import torch
+
+            tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int64: torch.int64,
+                   np.int32: torch.int32, np.uint64: torch.int64, np.uint32: torch.int32,
+                   np.uint16: torch.int16}[dtype]
+            if a.dtype != tdt or not a.is_contiguous() or not a.is_cuda:
+                raise TypeError(f"expected a contiguous CUDA tensor of {tdt}, got {a.dtype} on {a.device}")
+            if self.device is False:
+                raise TypeError("mixing host and device arrays in one call")
+            self.device = True
+            self.keep.append(a)
+            return a.data_ptr()
+        arr = np.ascontiguousarray(a, dtype=dtype)
+        if self.device is True:
+            raise TypeError("mixing host and device arrays in one call")
+        self.device = False
+        self.keep.append(arr)
+        return arr.ctypes.data
+
+    @property
+    def flags(self) -> int:
+        return DEVICE_PTR if self.device else 0
+
+
+def _search(d_lo, d_hi, eps, gamma=0.0, max_nodes=0, frontier_batch=0, frontier_capacity=0) -> SearchS:
+    return SearchS(float(d_lo), float(d_hi), float(eps), 0.0, float(gamma), int(max_nodes),
+                   int(frontier_batch), int(frontier_capacity))
+
+
+class Context:
+    """A library context on one GPU, ordered on a HIP stream (default: the
+    current torch stream of that device, when torch is loaded)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        if stream is None:
+            try:
+                import torch
+
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream(device).cuda_stream
+            except ImportError:  # pragma: no cover
+                stream = None
+        h = C.c_void_p()
+        rc = lib().ecmd_ctx_create(C.byref(h), int(device), C.c_void_p(stream or 0))
+        if rc != OK:
+            raise EcmdError(rc, "ecmd_ctx_create failed (no usable HIP device?)")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecmd_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc: int, allow=()):
+        if rc != OK and rc not in allow:
+            raise EcmdError(rc, lib().ecmd_last_error(self.h).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return lib().ecmd_last_error(self.h).decode()
+
+    # ---------------------------------------------------------- estimation
+    def estimate(self, sensor: Sensor, x, y, t, t0: float, t1: float, d_lo: float, d_hi: float, eps: float,
+                 gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0, frontier_capacity: int = 0,
+                 d_seed: Optional[float] = None) -> Result:
+        a = _Args()
+        n = int(x.shape[0])
+        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        seed = C.c_float(d_seed) if d_seed is not None else None
+        out = ResultS()
+        rc = lib().ecmd_estimate_divergence(self.h, C.byref(sensor), C.byref(ev), WindowS(t0, t1), C.byref(sp),
+                                            a.flags, C.byref(seed) if seed is not None else None, C.byref(out))
+        self._check(rc, allow=(EBUDGET, EFRONTIER))
+        return Result.of(out)
+
+    def estimate_batched(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
+                         eps: float, gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0,
+                         frontier_capacity: int = 0, d_seeds=None) -> list:
+        a = _Args()
+        B = int(tau.shape[0])
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        po, ptau = a.ptr(offsets, np.int64), a.ptr(tau, np.float32)
+        ps = a.ptr(d_seeds, np.float32) if d_seeds is not None else None
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        out = (ResultS * max(B, 1))()
+        rc = lib().ecmd_estimate_divergence_batched(self.h, C.byref(sensor), px, py, pt, po, ptau, B, C.byref(sp),
+                                                    a.flags, ps, out)
+        self._check(rc, allow=(EBUDGET, EFRONTIER))
+        return [Result.of(out[i]) for i in range(B)]
+
+    # -------------------------------------------------------------- probes
+    def probe_pixels(self, sensor: Sensor, x, y, t_rel, tau: float, d: float, out=None):
+        a = _Args()
+        n = int(x.shape[0])
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        if out is None:
+            out = _empty_like(x, n, np.int32)
+        po = a.ptr(out, np.int32)
+        self._check(lib().ecmd_probe_pixels(self.h, C.byref(sensor), px, py, pt, n, float(tau), float(d),
+                                            a.flags, po))
+        return out
+
+    def probe_point(self, sensor: Sensor, x, y, t_rel, tau: float, d, want_image: bool = False):
+        a = _Args()
+        n = int(x.shape[0])
+        m = int(d.shape[0])
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        pd = a.ptr(d, np.float32)
+        S = _empty_like(x, m, np.uint64)
+        N = _empty_like(x, m, np.int64)
+        img = _empty_like(x, m * sensor.width * sensor.height, np.uint32) if want_image else None
+        self._check(lib().ecmd_probe_point(self.h, C.byref(sensor), px, py, pt, n, float(tau), pd, m, a.flags,
+                                           a.ptr(S, np.uint64), a.ptr(N, np.int64),
+                                           a.ptr(img, np.uint32) if want_image else None))
+        return (S, N, img) if want_image else (S, N)
+
+    def probe_bound(self, sensor: Sensor, x, y, t_rel, tau: float, d_lo: float, d_hi: float, d_a, d_b,
+                    want_image: bool = False):
+        a = _Args()
+        n = int(x.shape[0])
+        m = int(d_a.shape[0])
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        pa, pb = a.ptr(d_a, np.float32), a.ptr(d_b, np.float32)
+        S = _empty_like(x, m, np.uint64)
+        N = _empty_like(x, m, np.int64)
+        img = _empty_like(x, m * sensor.width * sensor.height, np.uint32) if want_image else None
+        self._check(lib().ecmd_probe_bound(self.h, C.byref(sensor), px, py, pt, n, float(tau), float(d_lo),
+                                           float(d_hi), pa, pb, m, a.flags, a.ptr(S, np.uint64),
+                                           a.ptr(N, np.int64), a.ptr(img, np.uint32) if want_image else None))
+        return (S, N, img) if want_image else (S, N)
+
+    def downsample(self, sensor: Sensor, x, y, offsets):
+        a = _Args()
+        B = int(offsets.shape[0]) - 1
+        px, py, po = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(offsets, np.int64)
+        out = _empty_like(x, B * GRID * GRID, np.uint16)
+        self._check(lib().ecmd_downsample(self.h, C.byref(sensor), px, py, po, B, a.flags, a.ptr(out, np.uint16)))
+        return out
+
+
+def _empty_like(ref, n: int, dtype):
+    if _is_torch(ref):
+        import torch
+
+        tdt = {np.int32: torch.int32, np.int64: torch.int64, np.uint64: torch.int64, np.uint32: torch.int32,
+               np.uint16: torch.int16, np.float32: torch.float32}[dtype]
+        return torch.empty(n, dtype=tdt, device=ref.device)
+    return np.empty(n, dtype)
+
+
+def sensor(width: int, height: int, foe: Sequence[float]) -> Sensor:
+    return Sensor(int(width), int(height), float(foe[0]), float(foe[1]))
+
+
+def key(M: int, S: int, N: int) -> int:
+    return int(M) * int(S) - int(N) * int(N)
