@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact divergence estimator on one MI355X.
+
+Workload (one "step"): one batched call that certifies the canonical optimum
+of every window of a batch of synthetic ventral-descent windows on a 346x260
+sensor (100k events per 0.25 s window, 2000 textured surface points, 20%
+uniform noise, 0.5 px jitter, true D ~ U(0.05, 0.8)), searching D in
+[0, 1.5] with eps = 1e-5 (grid depth 18).  The step runs the whole hot path:
+event binning, point and interval evaluations, and the device frontier.
+Inputs are resident in HBM before the timed region starts.
+
+Printed: one JSON line with event-hypothesis evaluations per second (value),
+certified windows per second (batched, and plain one-window calls), the
+roofline of the hypothesis-evaluation kernel and the CPU oracle timed on a
+bounded sample of the same windows on this host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "event-hypothesis evals/sec; BnB windows/sec (plain vs batched+learned) at fixed eps"
+
+# Algorithmic VALU lane-operations of the fp32 statement per unit of work:
+OPS_POINT = 8      # per event and point hypothesis: 2 fma, 2 floor, 2 range tests, 1 index, 1 accumulate
+OPS_INTERVAL = 16  # per event and interval: 2 endpoint warps (4 fma, 4 floor), 4 range tests, 4 walk set-up
+OPS_PIXEL = 12     # per upper-bound pixel increment: corner test (7 fp64), 1 step, 2 range tests, 1 index, 1 acc
+# Peak lane-operation rate: 256 CUs x 64 lanes per clock (4 SIMDs x 16) x 2.4 GHz.
+PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--windows", type=int, default=32, help="windows per step")
+    ap.add_argument("--frontier-batch", type=int, default=0)
+    ap.add_argument("--plain-windows", type=int, default=8, help="windows timed one call each")
+    ap.add_argument("--cpu-windows", type=int, default=3, help="oracle sample size (windows)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the estimator has no multi-GPU path in this build "
+              "(windows would shard across GPUs with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+    from synth import config_windows, pack_batch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    B = args.windows
+    wins = config_windows("c2", range(B))
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    dx, dy, dt, doff, dtau = (torch.from_numpy(a).to(dev) for a in (x, y, t, off, tau))
+    sensor = ecmd.sensor(s.width, s.height, s.foe)
+    ctx = ecmd.Context(0)
+    kw = dict(frontier_batch=args.frontier_batch)
+
+    def step():
+        return ctx.estimate_batched(sensor, dx, dy, dt, doff, dtau, s.d_lo, s.d_hi, s.eps, **kw)
+
+    ref = None
+    for _ in range(args.warmup):
+        ref = step()
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.profile(reset=True)
+    t0 = time.perf_counter()
+    res = []
+    for _ in range(args.steps):
+        res.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(reset=True)
+    ctx.set_profiling(False)
+    sec = (t1 - t0) / args.steps
+    for r in res:  # deterministic results on every step
+        assert [(a.j_star, a.K) for a in r] == [(a.j_star, a.K) for a in (ref or res[0])]
+    last = res[-1]
+    assert all(r.status == 0 for r in last), [r.status for r in last]
+    ev_hyp = sum(r.event_hyp_evals for r in last)
+    n_w = np.array([r.n_events for r in last], np.int64)
+    pt_ev = sum(r.point_evals * r.n_events for r in last)
+    bd_ev = sum(r.bound_evals * r.n_events for r in last)
+    pix = sum(r.pixel_updates for r in last)
+    value = ev_hyp / sec
+
+    # plain: one window per call, no batching
+    P = min(args.plain_windows, B)
+    plain_t = []
+    for k in range(P):
+        w = wins[k]
+        px, py, pt, po, ptau = (torch.from_numpy(a).to(dev) for a in pack_batch([w]))
+        ctx.estimate_batched(sensor, px, py, pt, po, ptau, s.d_lo, s.d_hi, s.eps)  # warm
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        rp = ctx.estimate_batched(sensor, px, py, pt, po, ptau, s.d_lo, s.d_hi, s.eps)[0]
+        torch.cuda.synchronize()
+        plain_t.append(time.perf_counter() - a)
+        assert (rp.j_star, rp.K) == (last[k].j_star, last[k].K)
+
+    # roofline of the evaluation kernel (all its launches in the timed region)
+    ops_step = OPS_POINT * pt_ev + OPS_INTERVAL * bd_ev + OPS_PIXEL * pix
+    launches = max(prof["eval_launches"], 1)
+    avg_launch_s = prof["eval_ms"] / 1e3 / launches
+    ops_launch = ops_step * args.steps / launches
+    achieved = ops_launch / avg_launch_s if avg_launch_s > 0 else 0.0
+    roof = {
+        "bound": "alu",
+        "achieved": round(achieved / 1e9, 1),
+        "peak": round(PEAK_LANE_OPS / 1e9, 1),
+        "unit": "Gop/s (VALU lane-ops)",
+        "frac": round(achieved / PEAK_LANE_OPS, 4),
+        "traffic": None,
+        "kernel": "k_eval",
+        "avg_launch_us": round(avg_launch_s * 1e6, 2),
+        "launches_per_step": round(launches / args.steps, 2),
+        "eval_share_of_step": round(prof["eval_ms"] / 1e3 / args.steps / sec, 3),
+        "lds_atomics_per_s": round((pt_ev + pix) * args.steps / (prof["eval_ms"] / 1e3), 1)
+        if prof["eval_ms"] > 0 else None,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "event-hypothesis evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{B} windows of the 346x260 config per step: 100k events/0.25 s window, "
+                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB",
+            "windows_per_step": B,
+            "events_per_window": int(n_w.mean()),
+            "eps": s.eps,
+            "frontier_batch": args.frontier_batch or 64,
+        },
+        "windows_per_s": {
+            "batched": round(B / sec, 2),
+            "plain_one_window_per_call": round(P / sum(plain_t), 2),
+        },
+        "search": {
+            "nodes_expanded_mean": float(np.mean([r.nodes_expanded for r in last])),
+            "steps_max": int(max(r.steps for r in last)),
+            "point_event_evals": int(pt_ev),
+            "interval_event_evals": int(bd_ev),
+            "pixel_updates": int(pix),
+        },
+        "roofline": roof,
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+
+        nc = max(1, min(args.cpu_windows, B))
+        t_cpu = 0.0
+        ev_cpu = 0
+        for k in range(nc):
+            w = wins[k]
+            a = time.perf_counter()
+            o = O.bnb(O.Events.of_window(w), s.d_lo, s.d_hi, s.eps)
+            t_cpu += time.perf_counter() - a
+            ev_cpu += (o.point_evals + o.bound_evals) * w.n
+            assert (o.j_star, o.K) == (last[k].j_star, last[k].K), "GPU and oracle optima differ"
+        out["cpu_baseline"] = {
+            "value": round(ev_cpu / t_cpu, 1),
+            "unit": "event-hypothesis evals/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"{nc} of the step's windows, canonical BnB, single thread "
+                      f"({t_cpu:.1f} s, {nc / t_cpu:.3f} windows/s)",
+            "windows_per_s": round(nc / t_cpu, 4),
+        }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

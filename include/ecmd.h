@@ -132,6 +132,22 @@ const char *ecmd_last_error(const ecmd_ctx *ctx);
 /* Library version string. */
 const char *ecmd_version(void);
 
+/* Per-phase device timers of a context (HIP events on the context's
+ * stream around every launch of the phase; off by default).  Times are
+ * summed over all calls since the last reset. */
+typedef struct {
+    int64_t calls;
+    int64_t eval_launches;     /* hypothesis evaluation kernel (eqs. (13)-(20)) */
+    double eval_ms;
+    int64_t frontier_launches; /* frontier step kernel (Algorithm 1) */
+    double frontier_ms;
+    double prep_ms;            /* window prep (event binning) */
+} ecmd_profile;
+
+int ecmd_ctx_set_profiling(ecmd_ctx *ctx, int enable);
+/* Copy the accumulated timers; reset them when `reset` is non-zero. */
+int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
+
 /* ---------------------------------------------------------- estimation */
 
 /* One window (Algorithm 1 on the events with t in [t0, t1]).  d_seed

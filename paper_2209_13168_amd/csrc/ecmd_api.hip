@@ -89,6 +89,59 @@ struct ecmd_ctx {
     HostBuf pinned;
     std::vector<long long> h_off;
     std::vector<float> h_tau;
+    // phase timers
+    bool profiling = false;
+    ecmd_profile prof{};
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+};
+
+// Event pair around a launch when profiling (kind: 0 eval, 1 frontier, 2 prep).
+struct Mark {
+    hipEvent_t a, b;
+    int kind;
+};
+
+static hipEvent_t pool_event(ecmd_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+struct Timers {
+    ecmd_ctx* c;
+    std::vector<Mark> marks;
+    hipEvent_t pending = nullptr;
+    explicit Timers(ecmd_ctx* ctx) : c(ctx) { c->ev_used = 0; }
+    void begin() {
+        if (!c->profiling) return;
+        pending = pool_event(c);
+        if (pending) (void)hipEventRecord(pending, c->stream);
+    }
+    void end(int kind) {
+        if (!c->profiling || !pending) return;
+        hipEvent_t b = pool_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, c->stream);
+        marks.push_back(Mark{pending, b, kind});
+        pending = nullptr;
+    }
+    // after the stream has been synchronised
+    void collect() {
+        if (!c->profiling) return;
+        for (const Mark& m : marks) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, m.a, m.b) != hipSuccess) continue;
+            if (m.kind == 0) { c->prof.eval_ms += ms; c->prof.eval_launches += 1; }
+            else if (m.kind == 1) { c->prof.frontier_ms += ms; c->prof.frontier_launches += 1; }
+            else c->prof.prep_ms += ms;
+        }
+        c->prof.calls += 1;
+        marks.clear();
+    }
 };
 
 struct ecmd_cnn;  // defined in ecmd_cnn.hip
@@ -277,6 +330,13 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     return ECMD_OK;
 }
 
+// Largest tile (pixels) whose evaluation workgroup fits the LDS.
+static int tile_budget(ecmd_ctx* c) {
+    int px = (int)(c->max_lds / 4) - kEvalThreads - 64;
+    while (px > 0 && eval_lds_bytes(px) > c->max_lds) --px;
+    return px;
+}
+
 static int eval_blocks(ecmd_ctx* c, size_t lds) {
     int per_cu = 0;
     if (eval_occupancy(&per_cu, lds) != hipSuccess || per_cu < 1) per_cu = 1;
@@ -288,13 +348,15 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
                       const ecmd_search* search, int L, ecmd_result* out) {
     const int W = sensor->width, H = sensor->height;
     const long long M = (long long)W * H;
-    const int max_px = (int)((c->max_lds - 1024) / sizeof(unsigned));
     Geometry g;
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, max_px, g))
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), g))
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles);
+    Timers tm(c);
     int nblk = 0;
+    tm.begin();
     int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk);
     if (rc) return rc;
+    tm.end(2);
 
     Search sp;
     sp.d_lo = search->d_lo;
@@ -321,20 +383,24 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
                           c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[0], T,
                           c->seg_off.as<long long>()));
-    const size_t lds = (size_t)g.max_tile_px * sizeof(unsigned);
+    const size_t lds = eval_lds_bytes(g.max_tile_px);
     HIPCHK(c, eval_set_lds(lds));
     const int nb = eval_blocks(c, lds);
     int parity = 0;
     int* h_active = (int*)c->pinned.p;
     int active = B;
     for (int step = 0; step < kMaxSteps && active > 0; ++step) {
+        tm.begin();
         HIPCHK(c, launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
                               c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[parity],
                               &q[1 - parity], c->part.as<Part>(), sp.HS, nullptr));
+        tm.end(0);
+        tm.begin();
         HIPCHK(c, launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
                                   c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(),
                                   c->hyps.as<Hyp>(), c->part.as<Part>(), c->items.as<Item>(),
                                   &q[1 - parity], c->n_active.as<int>()));
+        tm.end(1);
         parity = 1 - parity;
         if ((step & 3) == 3) {
             HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -345,6 +411,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     std::vector<WinState> hs(B);
     HIPCHK(c, hipMemcpyAsync(hs.data(), c->state.p, sizeof(WinState) * B, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    tm.collect();
     int first_status = ECMD_OK;
     for (int w = 0; w < B; ++w) {
         const WinState& s = hs[w];
@@ -468,10 +535,24 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
                       &c->img, &c->keep, &c->counts, &c->misc};
     for (DevBuf* b : bufs) b->release();
     c->pinned.release();
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
 const char* ecmd_last_error(const ecmd_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int ecmd_ctx_set_profiling(ecmd_ctx* c, int enable) {
+    if (!c) return ECMD_EINVAL;
+    c->profiling = enable != 0;
+    return ECMD_OK;
+}
+
+int ecmd_ctx_get_profile(ecmd_ctx* c, ecmd_profile* out, int reset) {
+    if (!c || !out) return ECMD_EINVAL;
+    *out = c->prof;
+    if (reset) c->prof = ecmd_profile{};
+    return ECMD_OK;
+}
 
 int ecmd_estimate_divergence_batched(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y,
                                      const float* t_rel, const int64_t* offsets, const float* tau, int32_t B,
@@ -617,9 +698,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     HIPCHK(c, hipSetDevice(c->device));
     const int W = sensor->width, H = sensor->height;
     const long long M = (long long)W * H;
-    const int max_px = (int)((c->max_lds - 1024) / sizeof(unsigned));
     Geometry g;
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, max_px, g))
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), g))
         return fail(c, ECMD_EINVAL, "sensor needs more than %d tiles", kMaxTiles);
     const int T = g.T;
     Inputs in;
@@ -667,7 +747,7 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
             dimg = c->img.as<unsigned>();
         }
     }
-    const size_t lds = (size_t)g.max_tile_px * sizeof(unsigned);
+    const size_t lds = eval_lds_bytes(g.max_tile_px);
     HIPCHK(c, eval_set_lds(lds));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_eval(c->stream, g, eval_blocks(c, lds), lds, c->ev.as<float4>(), c->seg_off.as<long long>(),

@@ -23,7 +23,7 @@ namespace ecmd {
 typedef __int128 i128;
 
 constexpr int kMaxTiles = 64;    // tiles per sensor
-constexpr int kEvalThreads = 512;  // threads of an evaluation workgroup
+constexpr int kEvalThreads = 1024;  // threads of an evaluation workgroup
 constexpr int kFrontThreads = 256;  // threads of a frontier workgroup
 
 enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2 };
@@ -136,6 +136,8 @@ hipError_t launch_downsample(hipStream_t s, const float* x, const float* y, cons
                              int B, int W, int H, const int* blk_start, int nblk, int chunk,
                              unsigned* counts, uint16_t* out);
 hipError_t eval_set_lds(size_t bytes);
+// LDS bytes of the evaluation kernel for tiles of up to max_tile_px pixels.
+size_t eval_lds_bytes(int max_tile_px);
 hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes);
 // Events with t in [t0, t1], compacted in order, t_rel = float(t - t0).
 hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, long long n,

@@ -26,9 +26,18 @@ __device__ __forceinline__ bool inside(float xw, float yw, float Wf, float Hf) {
     return xw >= 0.0f && xw < Wf && yw >= 0.0f && yw < Hf;
 }
 
+// floor(v) as an integer in one instruction (saturating for huge |v|,
+// which only ever means "outside the image").
+__device__ __forceinline__ int cvt_flr(float v) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
 // floor of v clamped to [-1, hi]: -1 and hi both mean "outside the image"
-__device__ __forceinline__ int flr_clamp(float v, float hi) {
-    return (int)floorf(fminf(fmaxf(v, -1.0f), hi));
+// (floor commutes with clamping to integer limits).
+__device__ __forceinline__ int flr_clamp(float v, int hi) {
+    return min(max(cvt_flr(v), -1), hi);
 }
 
 __device__ __forceinline__ i128 mk128(long long hi, unsigned long long lo) {
@@ -106,11 +115,10 @@ __device__ __forceinline__ int band_of(const int* cut, int n, int k) {
 __device__ __forceinline__ bool event_tiles(const Geometry& g, float x, float y, float ax, float ay,
                                             float r_lo, float r_hi, int& tx0, int& tx1, int& ty0,
                                             int& ty1) {
-    const float Wf = (float)g.W, Hf = (float)g.H;
     float xa = fmaf(ax, r_lo, x), xb = fmaf(ax, r_hi, x);
     float ya = fmaf(ay, r_lo, y), yb = fmaf(ay, r_hi, y);
-    int kx0 = flr_clamp(fminf(xa, xb), Wf), kx1 = flr_clamp(fmaxf(xa, xb), Wf);
-    int ky0 = flr_clamp(fminf(ya, yb), Hf), ky1 = flr_clamp(fmaxf(ya, yb), Hf);
+    int kx0 = flr_clamp(fminf(xa, xb), g.W), kx1 = flr_clamp(fmaxf(xa, xb), g.W);
+    int ky0 = flr_clamp(fminf(ya, yb), g.H), ky1 = flr_clamp(fmaxf(ya, yb), g.H);
     if (kx1 < 0 || kx0 > g.W - 1 || ky1 < 0 || ky0 > g.H - 1) return false;
     kx0 = max(kx0, 0); ky0 = max(ky0, 0);
     kx1 = min(kx1, g.W - 1); ky1 = min(ky1, g.H - 1);
@@ -273,23 +281,23 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // Add one to every pixel of this tile that the staircase walk from pixel
 // (kxa, kya) to pixel (kxb, kyb) visits (eq. (17)).  Corner decisions follow
 // the event's ray through (x, y) with direction (ax, ay), in fp64; within
-// 2^-8 px of a corner both side pixels are counted.
-__device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, int x0, int y0, unsigned tw,
-                                          unsigned th, int kxa, int kya, int kxb, int kyb, double x,
-                                          double y, double ax, double ay,
-                                          unsigned long long& sumold, unsigned long long& hits) {
+// 2^-8 px of a corner both side pixels are counted.  Pixels outside the
+// tile increment the thread's private spill word `spill` instead, whose
+// returned counts are removed at the end (see k_eval).
+__device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned spill, int x0, int y0,
+                                          unsigned tw, unsigned th, int kxa, int kya, int kxb, int kyb,
+                                          double x, double y, double ax, double ay,
+                                          unsigned long long& sumold, unsigned& visits) {
     const int sx = (kxb > kxa) - (kxb < kxa);
     const int sy = (kyb > kya) - (kyb < kya);
     const double thr = (fabs(ax) + fabs(ay)) * 0.00390625;
     const double aax = fabs(ax), aay = fabs(ay);
     int kx = kxa, ky = kya;
     auto visit = [&](int px, int py) {
-        unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
-        if (lx < tw && ly < th) {
-            unsigned old = atomicAdd(&tile[ly * tw + lx], 1u);
-            sumold += old;
-            hits += 1;
-        }
+        const unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
+        const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
+        sumold += atomicAdd(&tile[a], 1u);
+        visits += 1;
     };
     visit(kx, ky);
     while (kx != kxb || ky != kyb) {
@@ -318,15 +326,30 @@ __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, int x0, i
     }
 }
 
+// LDS layout of k_eval: [tile: tw*th counters][spill: one word per thread]
+// [reduction scratch][work item].
+constexpr int kEvalWaves = kEvalThreads / 64;
+
+size_t eval_lds_bytes(int max_tile_px) {
+    return (size_t)(max_tile_px + kEvalThreads) * 4 + 3 * kEvalWaves * 8 + 16;
+}
+
+// Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
+// items from the queue until it is empty.  For each item it clears its LDS
+// tile, bins the tile's events (point: one increment per event, interval:
+// one per pixel of the walk) with atomics that return the previous count,
+// so the sum of squares is sum(2*old + 1) with no pass over the tile.
 __global__ __launch_bounds__(kEvalThreads) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
     const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const Item* __restrict__ items,
     Queue* __restrict__ q, Queue* __restrict__ q_reset, Part* __restrict__ part, int HS,
     unsigned* __restrict__ img_out) {
-    extern __shared__ unsigned tile[];
-    __shared__ int s_item;
-    __shared__ unsigned long long s_red[3][kEvalThreads / 64];
+    extern __shared__ unsigned smem[];
     const int tid = threadIdx.x;
+    unsigned* const tile = smem;
+    unsigned long long* const s_red =
+        reinterpret_cast<unsigned long long*>(smem + g.max_tile_px + kEvalThreads);
+    int* const s_item = reinterpret_cast<int*>(s_red + 3 * kEvalWaves);
     if (blockIdx.x == 0 && tid == 0 && q_reset) {
         q_reset->n_items = 0;
         q_reset->next = 0;
@@ -334,9 +357,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     const int n_items = q->n_items;
     const float Wf = (float)g.W, Hf = (float)g.H;
     for (;;) {
-        if (tid == 0) s_item = atomicAdd(&q->next, 1);
+        if (tid == 0) *s_item = atomicAdd(&q->next, 1);
         __syncthreads();
-        const int it = s_item;
+        const int it = *s_item;
         __syncthreads();
         if (it >= n_items) break;
         const Item item = items[it];
@@ -346,54 +369,88 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const int x0 = g.colcut[tx], y0 = g.rowcut[ty];
         const unsigned tw = (unsigned)(g.colcut[tx + 1] - x0), th = (unsigned)(g.rowcut[ty + 1] - y0);
         const int npx = (int)(tw * th);
+        const unsigned spill = (unsigned)npx + (unsigned)tid;  // this thread's private word
         const long long seg = (long long)w * g.T + t;
         const long long beg = seg_off[seg], end = seg_off[seg + 1];
         const long long own_end = beg + seg_own[seg];
 
-        for (int i = tid; i < npx; i += kEvalThreads) tile[i] = 0u;
+        for (int i = tid; i < npx + kEvalThreads; i += kEvalThreads) tile[i] = 0u;
         __syncthreads();
 
-        unsigned long long sumold = 0, hits = 0, nlow = 0;
+        unsigned long long sumold = 0, nlow = 0;
+        unsigned visits = 0;
         if (hp.kind == HYP_POINT) {
+            // Point hypothesis (eqs. (12)-(13)): U events per thread in
+            // flight, loads first, then U increments without branches.
             const float r = hp.ra;
-#pragma unroll 4
-            for (long long i = beg + tid; i < end; i += kEvalThreads) {
-                const float4 e = ev[i];
-                const float xw = fmaf(e.z, r, e.x), yw = fmaf(e.w, r, e.y);
-                const unsigned lx = (unsigned)(flr_clamp(xw, Wf) - x0);
-                const unsigned ly = (unsigned)(flr_clamp(yw, Hf) - y0);
-                if (lx < tw && ly < th) {
-                    unsigned old = atomicAdd(&tile[ly * tw + lx], 1u);
-                    sumold += old;
-                    hits += 1;
+            constexpr int U = 4;
+            constexpr long long S = kEvalThreads;
+            long long i = beg + tid;
+            for (; i + (U - 1) * S < end; i += U * S) {
+                float4 e[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) e[k] = ev[i + k * S];
+                unsigned a[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const unsigned lx = (unsigned)(cvt_flr(fmaf(e[k].z, r, e[k].x)) - x0);
+                    const unsigned ly = (unsigned)(cvt_flr(fmaf(e[k].w, r, e[k].y)) - y0);
+                    a[k] = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
                 }
+                unsigned old[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) old[k] = atomicAdd(&tile[a[k]], 1u);
+#pragma unroll
+                for (int k = 0; k < U; ++k) sumold += old[k];
+                visits += U;
+            }
+            for (; i < end; i += S) {
+                const float4 e = ev[i];
+                const unsigned lx = (unsigned)(cvt_flr(fmaf(e.z, r, e.x)) - x0);
+                const unsigned ly = (unsigned)(cvt_flr(fmaf(e.w, r, e.y)) - y0);
+                const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
+                sumold += atomicAdd(&tile[a], 1u);
+                visits += 1;
             }
         } else {
+            // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
-            for (long long i = beg + tid; i < end; i += kEvalThreads) {
-                const float4 e = ev[i];
+            long long i = beg + tid;
+            float4 e = i < end ? ev[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (; i < end; i += kEvalThreads) {
+                const long long inext = i + kEvalThreads;
+                const float4 en = inext < end ? ev[inext] : e;  // prefetch while walking
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
                 if (i < own_end && inside(xa, ya, Wf, Hf) && inside(xb, yb, Wf, Hf)) nlow += 1;
-                walk_tile(tile, x0, y0, tw, th, flr_clamp(xa, Wf), flr_clamp(ya, Hf), flr_clamp(xb, Wf),
-                          flr_clamp(yb, Hf), (double)e.x, (double)e.y, (double)e.z, (double)e.w, sumold,
-                          hits);
+                walk_tile(tile, spill, x0, y0, tw, th, flr_clamp(xa, g.W), flr_clamp(ya, g.H),
+                          flr_clamp(xb, g.W), flr_clamp(yb, g.H), (double)e.x, (double)e.y, (double)e.z,
+                          (double)e.w, sumold, visits);
+                e = en;
             }
         }
+        // Remove the spill word: its m increments returned 0, 1, .., m-1.
+        const unsigned m = tile[spill];
+        sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
+        unsigned long long hits = (unsigned long long)(visits - m);
         // block reduction of (sumold, hits, nlow)
         sumold = wave_sum(sumold);
         hits = wave_sum(hits);
         nlow = wave_sum(nlow);
         const int wave = tid >> 6, lane = tid & 63;
         if (lane == 0) {
-            s_red[0][wave] = sumold;
-            s_red[1][wave] = hits;
-            s_red[2][wave] = nlow;
+            s_red[wave] = sumold;
+            s_red[kEvalWaves + wave] = hits;
+            s_red[2 * kEvalWaves + wave] = nlow;
         }
         __syncthreads();
         if (tid == 0) {
             unsigned long long a = 0, b = 0, c = 0;
-            for (int k = 0; k < kEvalThreads / 64; ++k) { a += s_red[0][k]; b += s_red[1][k]; c += s_red[2][k]; }
+            for (int k = 0; k < kEvalWaves; ++k) {
+                a += s_red[k];
+                b += s_red[kEvalWaves + k];
+                c += s_red[2 * kEvalWaves + k];
+            }
             Part pt;
             pt.S = 2ull * a + b;
             pt.N = (long long)(hp.kind == HYP_POINT ? b : c);
@@ -403,9 +460,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         }
         if (img_out) {
             const long long M = (long long)g.W * g.H;
-            for (int i = tid; i < npx; i += kEvalThreads) {
-                int lx = i % (int)tw, ly = i / (int)tw;
-                img_out[(long long)item.wh * M + (long long)(y0 + ly) * g.W + (x0 + lx)] = tile[i];
+            for (int k = tid; k < npx; k += kEvalThreads) {
+                int lx = k % (int)tw, ly = k / (int)tw;
+                img_out[(long long)item.wh * M + (long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
             }
         }
     }

@@ -59,6 +59,11 @@ class ResultS(C.Structure):
                 ("steps", C.c_int32), ("seeded", C.c_int32)]
 
 
+class ProfileS(C.Structure):
+    _fields_ = [("calls", C.c_int64), ("eval_launches", C.c_int64), ("eval_ms", C.c_double),
+                ("frontier_launches", C.c_int64), ("frontier_ms", C.c_double), ("prep_ms", C.c_double)]
+
+
 @dataclass
 class Result:
     status: int
@@ -107,6 +112,8 @@ def _load():
         "ecmd_probe_bound": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, f32, f32, vp, vp, i32, u32,
                               vp, vp, vp], C.c_int),
         "ecmd_downsample": ([vp, C.POINTER(Sensor), vp, vp, vp, i32, u32, vp], C.c_int),
+        "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
+        "ecmd_ctx_get_profile": ([vp, C.POINTER(ProfileS), C.c_int], C.c_int),
         "ecmd_cnn_create": ([vp, C.c_uint64, C.POINTER(vp)], C.c_int),
         "ecmd_cnn_destroy": ([vp], None),
         "ecmd_cnn_get_params": ([vp, vp], C.c_int),
@@ -225,6 +232,14 @@ class Context:
 
     def last_error(self) -> str:
         return lib().ecmd_last_error(self.h).decode()
+
+    def set_profiling(self, enable: bool = True):
+        self._check(lib().ecmd_ctx_set_profiling(self.h, 1 if enable else 0))
+
+    def profile(self, reset: bool = False) -> dict:
+        p = ProfileS()
+        self._check(lib().ecmd_ctx_get_profile(self.h, C.byref(p), 1 if reset else 0))
+        return {f[0]: getattr(p, f[0]) for f in ProfileS._fields_}
 
     # ---------------------------------------------------------- estimation
     def estimate(self, sensor: Sensor, x, y, t, t0: float, t1: float, d_lo: float, d_hi: float, eps: float,
