@@ -144,7 +144,11 @@ struct Timers {
     }
 };
 
-struct ecmd_cnn;  // defined in ecmd_cnn.hip
+struct ecmd_cnn {
+    ecmd_ctx* ctx = nullptr;
+    DevBuf P, m, v, grad, pg, lossb, loss, out, imgs, labels, seeds;
+    int step = 0;
+};
 
 static int fail(ecmd_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -870,6 +874,201 @@ int ecmd_downsample(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, cons
         HIPCHK(c, hipMemcpyAsync(out, dout, sizeof(uint16_t) * (size_t)B * 4096, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return ECMD_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ learned incumbent
+
+// Deterministic parameter initialisation: He-normal weights from a
+// splitmix64 stream (Box-Muller), zero biases.
+static void cnn_init_params(uint64_t seed, std::vector<float>& p) {
+    const int n = cnn_nparam();
+    p.assign(n, 0.0f);
+    uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto unif = [&]() { return ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); };
+    auto normal = [&]() { return sqrt(-2.0 * log(unif())) * cos(6.283185307179586 * unif()); };
+    struct Seg { int off, n, fan_in; };
+    const Seg segs[] = {{0, 144, 9}, {160, 4608, 144}, {4800, 18432, 288}, {23296, 64, 64}};
+    for (const Seg& sg : segs)
+        for (int k = 0; k < sg.n; ++k) p[sg.off + k] = (float)(normal() * sqrt(2.0 / sg.fan_in));
+}
+
+static int cnn_stage_imgs(ecmd_cnn* n, const uint16_t* imgs, int32_t B, uint32_t flags, const uint16_t** out) {
+    ecmd_ctx* c = n->ctx;
+    const void* p;
+    int rc = stage(c, n->imgs, imgs, sizeof(uint16_t) * (size_t)B * 4096, flags, &p);
+    *out = (const uint16_t*)p;
+    return rc;
+}
+
+// forward (mode 0) or forward + backward with the batch gradient in n->grad
+static int cnn_run(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32_t B, uint32_t flags, int mode) {
+    ecmd_ctx* c = n->ctx;
+    if (B <= 0 || !imgs || (mode && !labels)) return fail(c, ECMD_EINVAL, "bad network arguments");
+    HIPCHK(c, hipSetDevice(c->device));
+    const uint16_t* di;
+    int rc = cnn_stage_imgs(n, imgs, B, flags, &di);
+    if (rc) return rc;
+    HIPCHK(c, n->out.ensure(sizeof(float) * B));
+    const float* dl = nullptr;
+    if (mode) {
+        const void* p;
+        if ((rc = stage(c, n->labels, labels, sizeof(float) * B, flags, &p))) return rc;
+        dl = (const float*)p;
+        HIPCHK(c, n->pg.ensure(sizeof(float) * (size_t)B * cnn_nparam()));
+        HIPCHK(c, n->lossb.ensure(sizeof(float) * B));
+        HIPCHK(c, n->loss.ensure(sizeof(float)));
+        HIPCHK(c, n->grad.ensure(sizeof(float) * cnn_nparam()));
+    }
+    HIPCHK(c, cnn_set_lds());
+    HIPCHK(c, launch_cnn(c->stream, n->P.as<float>(), di, B, n->out.as<float>(), mode, dl, n->pg.as<float>(),
+                         n->lossb.as<float>()));
+    if (mode)
+        HIPCHK(c, launch_cnn_reduce(c->stream, n->pg.as<float>(), n->lossb.as<float>(), B, n->grad.as<float>(),
+                                    n->loss.as<float>()));
+    return ECMD_OK;
+}
+
+extern "C" {
+
+int ecmd_cnn_create(ecmd_ctx* c, uint64_t seed, ecmd_cnn** out) {
+    if (!c || !out) return ECMD_EINVAL;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    ecmd_cnn* n = new (std::nothrow) ecmd_cnn();
+    if (!n) return fail(c, ECMD_ENOMEM, "host allocation failed");
+    n->ctx = c;
+    const int np = cnn_nparam();
+    std::vector<float> p;
+    cnn_init_params(seed, p);
+    std::vector<float> zero(np, 0.0f);
+    if (n->P.ensure(sizeof(float) * np) != hipSuccess || n->m.ensure(sizeof(float) * np) != hipSuccess ||
+        n->v.ensure(sizeof(float) * np) != hipSuccess) {
+        n->P.release(); n->m.release(); n->v.release();
+        delete n;
+        return fail(c, ECMD_ENOMEM, "device allocation failed");
+    }
+    HIPCHK(c, hipMemcpy(n->P.p, p.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(n->m.p, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(n->v.p, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    *out = n;
+    return ECMD_OK;
+}
+
+void ecmd_cnn_destroy(ecmd_cnn* n) {
+    if (!n) return;
+    (void)hipSetDevice(n->ctx->device);
+    (void)hipStreamSynchronize(n->ctx->stream);
+    DevBuf* bufs[] = {&n->P, &n->m, &n->v, &n->grad, &n->pg, &n->lossb, &n->loss, &n->out, &n->imgs, &n->labels,
+                      &n->seeds};
+    for (DevBuf* b : bufs) b->release();
+    delete n;
+}
+
+int ecmd_cnn_get_params(ecmd_cnn* n, float* host_params) {
+    if (!n || !host_params) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(host_params, n->P.p, sizeof(float) * cnn_nparam(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+int ecmd_cnn_set_params(ecmd_cnn* n, const float* host_params) {
+    if (!n || !host_params) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    for (int k = 0; k < cnn_nparam(); ++k)
+        if (!isfinite(host_params[k])) return fail(c, ECMD_EINVAL, "parameter %d is not finite", k);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(n->P.p, host_params, sizeof(float) * cnn_nparam(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+int ecmd_cnn_forward(ecmd_cnn* n, const uint16_t* imgs, int32_t B, uint32_t flags, float* d_out) {
+    if (!n || !d_out) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    c->err.clear();
+    int rc = cnn_run(n, imgs, nullptr, B, flags, 0);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(d_out, n->out.p, sizeof(float) * B,
+                             (flags & ECMD_DEVICE_PTR) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+int ecmd_cnn_grads(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32_t B, uint32_t flags,
+                   float* grad_out, float* loss_out) {
+    if (!n || !grad_out || !loss_out) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    c->err.clear();
+    int rc = cnn_run(n, imgs, labels, B, flags, 1);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(grad_out, n->grad.p, sizeof(float) * cnn_nparam(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(loss_out, n->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+int ecmd_cnn_train_step(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32_t B, float lr, uint32_t flags,
+                        float* loss_out) {
+    if (!n) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    c->err.clear();
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(c, ECMD_EINVAL, "learning rate must be > 0");
+    int rc = cnn_run(n, imgs, labels, B, flags, 1);
+    if (rc) return rc;
+    n->step += 1;
+    HIPCHK(c, launch_adam(c->stream, n->P.as<float>(), n->m.as<float>(), n->v.as<float>(), n->grad.as<float>(), lr,
+                          n->step));
+    if (loss_out) {
+        HIPCHK(c, hipMemcpyAsync(loss_out, n->loss.p, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+int ecmd_estimate_divergence_learned(ecmd_ctx* c, ecmd_cnn* n, const ecmd_sensor* sensor, const float* x,
+                                     const float* y, const float* t_rel, const int64_t* offsets, const float* tau,
+                                     int32_t B, const ecmd_search* search, uint32_t flags, ecmd_result* out) {
+    if (!c || !n || n->ctx != c) return c ? fail(c, ECMD_EINVAL, "network belongs to another context") : ECMD_EINVAL;
+    c->err.clear();
+    if (B <= 0) return B == 0 ? ECMD_OK : fail(c, ECMD_EINVAL, "B < 0");
+    if (!search) return fail(c, ECMD_EINVAL, "search is NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    // downsampled images stay on the device
+    HIPCHK(c, n->imgs.ensure(sizeof(uint16_t) * (size_t)B * 4096));
+    HIPCHK(c, n->seeds.ensure(sizeof(float) * B));
+    int rc;
+    if (flags & ECMD_DEVICE_PTR) {
+        rc = ecmd_downsample(c, sensor, x, y, offsets, B, flags, n->imgs.as<uint16_t>());
+    } else {
+        std::vector<uint16_t> tmp((size_t)B * 4096);
+        rc = ecmd_downsample(c, sensor, x, y, offsets, B, 0, tmp.data());
+        if (!rc) {
+            HIPCHK(c, hipMemcpyAsync(n->imgs.p, tmp.data(), sizeof(uint16_t) * tmp.size(), hipMemcpyHostToDevice,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    if (rc) return rc;
+    rc = cnn_run(n, n->imgs.as<uint16_t>(), nullptr, B, ECMD_DEVICE_PTR, 0);
+    if (rc) return rc;
+    HIPCHK(c, launch_seed_from_pred(c->stream, n->out.as<float>(), B, search->d_lo, search->d_hi,
+                                    n->seeds.as<float>()));
+    if (flags & ECMD_DEVICE_PTR)
+        return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, n->seeds.as<float>(), out);
+    std::vector<float> hs(B);
+    HIPCHK(c, hipMemcpyAsync(hs.data(), n->seeds.p, sizeof(float) * B, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, hs.data(), out);
 }
 
 }  // extern "C"

@@ -144,4 +144,14 @@ hipError_t launch_select(hipStream_t s, const float* x, const float* y, const do
                          double t0, double t1, float* xo, float* yo, float* to, int* blk_cnt,
                          long long* total);
 
+// learned incumbent (ecmd_cnn.hip)
+size_t cnn_lds_bytes();
+int cnn_nparam();
+hipError_t cnn_set_lds();
+hipError_t launch_cnn(hipStream_t s, const float* P, const uint16_t* imgs, int B, float* out, int mode,
+                      const float* labels, float* pg, float* lossb);
+hipError_t launch_cnn_reduce(hipStream_t s, const float* pg, const float* lossb, int B, float* grad, float* loss);
+hipError_t launch_adam(hipStream_t s, float* P, float* m, float* v, const float* grad, float lr, int step);
+hipError_t launch_seed_from_pred(hipStream_t s, const float* pred, int B, float d_lo, float d_hi, float* seeds);
+
 }  // namespace ecmd

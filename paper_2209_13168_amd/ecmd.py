@@ -312,6 +312,21 @@ class Context:
                                            a.ptr(N, np.int64), a.ptr(img, np.uint32) if want_image else None))
         return (S, N, img) if want_image else (S, N)
 
+    def estimate_learned(self, cnn: "Cnn", sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
+                         eps: float, gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0,
+                         frontier_capacity: int = 0) -> list:
+        """Batched estimation whose incumbents are seeded by the network."""
+        a = _Args()
+        B = int(tau.shape[0])
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        po, ptau = a.ptr(offsets, np.int64), a.ptr(tau, np.float32)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        out = (ResultS * max(B, 1))()
+        rc = lib().ecmd_estimate_divergence_learned(self.h, cnn.h, C.byref(sensor), px, py, pt, po, ptau, B,
+                                                    C.byref(sp), a.flags, out)
+        self._check(rc, allow=(EBUDGET, EFRONTIER))
+        return [Result.of(out[i]) for i in range(B)]
+
     def downsample(self, sensor: Sensor, x, y, offsets):
         a = _Args()
         B = int(offsets.shape[0]) - 1
@@ -319,6 +334,62 @@ class Context:
         out = _empty_like(x, B * GRID * GRID, np.uint16)
         self._check(lib().ecmd_downsample(self.h, C.byref(sensor), px, py, po, B, a.flags, a.ptr(out, np.uint16)))
         return out
+
+
+class Cnn:
+    """The learned-incumbent network of a context (parameters on the GPU)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        h = C.c_void_p()
+        ctx._check(lib().ecmd_cnn_create(ctx.h, C.c_uint64(seed), C.byref(h)))
+        self.h = h
+        self.ctx = ctx
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecmd_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        p = np.empty(CNN_NPARAM, np.float32)
+        self.ctx._check(lib().ecmd_cnn_get_params(self.h, p.ctypes.data))
+        return p
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.shape == (CNN_NPARAM,)
+        self.ctx._check(lib().ecmd_cnn_set_params(self.h, p.ctypes.data))
+
+    def forward(self, imgs):
+        a = _Args()
+        B = int(imgs.shape[0]) if imgs.ndim > 1 else int(imgs.shape[0]) // (GRID * GRID)
+        pi = a.ptr(imgs, np.uint16)
+        out = _empty_like(imgs, B, np.float32)
+        self.ctx._check(lib().ecmd_cnn_forward(self.h, pi, B, a.flags, a.ptr(out, np.float32)))
+        return out
+
+    def grads(self, imgs, labels):
+        a = _Args()
+        B = int(labels.shape[0])
+        pi, pl = a.ptr(imgs, np.uint16), a.ptr(labels, np.float32)
+        g = np.empty(CNN_NPARAM, np.float32)
+        loss = C.c_float()
+        self.ctx._check(lib().ecmd_cnn_grads(self.h, pi, pl, B, a.flags, g.ctypes.data, C.byref(loss)))
+        return g, float(loss.value)
+
+    def train_step(self, imgs, labels, lr: float) -> float:
+        a = _Args()
+        B = int(labels.shape[0])
+        pi, pl = a.ptr(imgs, np.uint16), a.ptr(labels, np.float32)
+        loss = C.c_float()
+        self.ctx._check(lib().ecmd_cnn_train_step(self.h, pi, pl, B, float(lr), a.flags, C.byref(loss)))
+        return float(loss.value)
 
 
 def _empty_like(ref, n: int, dtype):

@@ -1,0 +1,86 @@
+"""The learned-incumbent network on the GPU against its CPU statement."""
+
+import numpy as np
+import pytest
+
+from synth import config_windows, pack_batch
+from tests.test_oracle_cnn import _rand
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2209_13168_amd import ecmd
+
+    c = ecmd.Context(0)
+    yield c
+    c.close()
+
+
+def test_forward_matches_cpu_statement(ctx):
+    from oracle import cnn as ocnn
+    from paper_2209_13168_amd import ecmd
+
+    net = ecmd.Cnn(ctx, seed=3)
+    for seed in (0, 1):
+        p, x, _ = _rand(seed, B=16)
+        net.set_params(p)
+        got = net.forward(x.reshape(16, -1))
+        want = ocnn.predict(p, x)
+        assert np.allclose(got, want, rtol=5e-3, atol=2e-3), np.abs(got - want).max()
+    net.close()
+
+
+def test_gradients_match_cpu_statement(ctx):
+    """Per-layer relative error of the batch gradient (bfloat16 layer inputs,
+    fp32 sums) against the fp64 statement with the same roundings."""
+    from oracle import cnn as ocnn
+    from paper_2209_13168_amd import ecmd
+
+    net = ecmd.Cnn(ctx, seed=4)
+    p, x, y = _rand(5, B=8)
+    net.set_params(p)
+    g, loss = net.grads(x.reshape(8, -1), y)
+    loss_o, g_o, _ = ocnn.loss_and_grad(p, x, y, rounding=True)
+    assert loss == pytest.approx(loss_o, rel=1e-2)
+    k = 0
+    for name, shape in ocnn.SHAPES:
+        n = int(np.prod(shape))
+        a, b = g[k:k + n].astype(np.float64), g_o[k:k + n]
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        assert rel <= 1e-2, (name, rel)
+        k += n
+    net.close()
+
+
+def test_training_reduces_the_loss(ctx):
+    from paper_2209_13168_amd import ecmd
+
+    ws = config_windows("c4", range(64), n_events=20_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    imgs = ctx.downsample(ecmd.sensor(s.width, s.height, s.foe), x, y, off).reshape(len(ws), -1)
+    labels = np.array([w.spec.d_true for w in ws], np.float32)
+    net = ecmd.Cnn(ctx, seed=7)
+    first = net.train_step(imgs, labels, 1e-3)
+    for _ in range(150):
+        last = net.train_step(imgs, labels, 1e-3)
+    assert last < 0.5 * first, (first, last)
+    net.close()
+
+
+def test_learned_seeding_keeps_the_certified_optimum(ctx, orc):
+    from paper_2209_13168_amd import ecmd
+
+    ws = config_windows("c4", range(1_000_000, 1_000_004), n_events=15_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    sen = ecmd.sensor(s.width, s.height, s.foe)
+    net = ecmd.Cnn(ctx, seed=1)
+    learned = ctx.estimate_learned(net, sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+    for w, r in zip(ws, learned):
+        o = orc.bnb(orc.Events.of_window(w), s.d_lo, s.d_hi, 1e-4)
+        assert r.status == 0 and (r.j_star, r.K) == (o.j_star, o.K)
+        assert r.seeded == 1
+    net.close()
