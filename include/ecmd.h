@@ -148,6 +148,30 @@ int ecmd_ctx_set_profiling(ecmd_ctx *ctx, int enable);
 /* Copy the accumulated timers; reset them when `reset` is non-zero. */
 int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
 
+/* Launch tuning of a context, used by every search call whose
+ * ecmd_search.frontier_batch is 0.  frontier_batch: nodes expanded together
+ * per window and step (0 = 64).  tile_px: largest image tile per LDS
+ * histogram (0 = what the LDS holds; smaller values split the FOE quadrants
+ * further, trading guest copies for occupancy).  graph: replay the step
+ * loop as a captured hipGraph (0 = plain launches). */
+typedef struct {
+    int32_t frontier_batch;
+    int32_t tile_px;
+    int32_t graph;
+    int32_t reserved;
+} ecmd_tuning;
+
+int ecmd_ctx_set_tuning(ecmd_ctx *ctx, const ecmd_tuning *tuning);
+int ecmd_ctx_get_tuning(const ecmd_ctx *ctx, ecmd_tuning *out);
+
+/* Autotuner: times candidate tunings (frontier batch, tile size, graph
+ * replay) on the given batch (arguments as ecmd_estimate_divergence_batched,
+ * with search->frontier_batch ignored), keeps the fastest in the context and
+ * writes it to `best`; ms_best (nullable) receives its time per call. */
+int ecmd_autotune(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x, const float *y,
+                  const float *t_rel, const int64_t *offsets, const float *tau, int32_t B,
+                  const ecmd_search *search, uint32_t flags, ecmd_tuning *best, double *ms_best);
+
 /* ---------------------------------------------------------- estimation */
 
 /* One window (Algorithm 1 on the events with t in [t0, t1]).  d_seed

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -89,6 +90,11 @@ struct ecmd_ctx {
     HostBuf pinned;
     std::vector<long long> h_off;
     std::vector<float> h_tau;
+    // launch tuning and the captured step graph
+    ecmd_tuning tune{};
+    hipStream_t own_stream = nullptr;  // work stream when the caller gives the null stream
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
     // phase timers
     bool profiling = false;
     ecmd_profile prof{};
@@ -303,20 +309,19 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     HIPCHK(c, c->pinned.ensure(sizeof(int) * (B + 1) + 64));
     memcpy(c->pinned.p, blk.data(), sizeof(int) * (B + 1));
     HIPCHK(c, hipMemcpyAsync(c->blk.p, c->pinned.p, sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, c->cnt_own.ensure(sizeof(int) * B * T));
-    HIPCHK(c, c->cnt_guest.ensure(sizeof(int) * B * T));
+    const size_t nctr = prep_counters(B, T);
+    HIPCHK(c, c->cnt_own.ensure(sizeof(int) * nctr));
     HIPCHK(c, c->seg_off.ensure(sizeof(long long) * (B * T + 1)));
     HIPCHK(c, c->seg_own.ensure(sizeof(int) * B * T));
-    HIPCHK(c, c->cursor.ensure(sizeof(unsigned long long) * 2 * B * T));
+    HIPCHK(c, c->cursor.ensure(sizeof(unsigned long long) * nctr));
     HIPCHK(c, c->err_flag.ensure(sizeof(int)));
-    HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * B * T, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->cnt_guest.p, 0, sizeof(int) * B * T, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream));
     HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
-    HIPCHK(c, launch_winparam(c->stream, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
+    HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
     // count + scan (scatter needs the total to size the event store)
     HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
-                          nblk, kChunk, c->cnt_own.as<int>(), c->cnt_guest.as<int>(), c->seg_off.as<long long>(),
-                          c->seg_own.as<int>(), c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>()));
+                          nblk, kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
+                          c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>()));
     HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync((char*)c->pinned.p + 8, c->err_flag.p, sizeof(int), hipMemcpyDeviceToHost,
@@ -328,7 +333,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
         return fail(c, ECMD_EINVAL, "an event has a non-finite coordinate or t_rel outside [0, tau]");
     HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)std::max(total, 1ll)));
     HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
-                          nblk, kChunk, nullptr, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
+                          nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
                           c->ev.as<float4>(), nullptr));
     *nblk_out = nblk;
     return ECMD_OK;
@@ -353,7 +358,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     const int W = sensor->width, H = sensor->height;
     const long long M = (long long)W * H;
     Geometry g;
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), g))
+    const int budget = c->tune.tile_px > 0 ? std::min(c->tune.tile_px, tile_budget(c)) : tile_budget(c);
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, g))
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles);
     Timers tm(c);
     int nblk = 0;
@@ -366,7 +372,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.d_lo = search->d_lo;
     sp.d_hi = search->d_hi;
     sp.L = L;
-    sp.F = search->frontier_batch > 0 ? search->frontier_batch : kDefaultF;
+    sp.F = search->frontier_batch > 0 ? search->frontier_batch
+                                      : (c->tune.frontier_batch > 0 ? c->tune.frontier_batch : kDefaultF);
     sp.CAP = search->frontier_capacity > 0 ? search->frontier_capacity : kDefaultCap;
     sp.HS = 3 * sp.F;
     sp.max_nodes = search->max_nodes;
@@ -390,27 +397,67 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     const size_t lds = eval_lds_bytes(g.max_tile_px);
     HIPCHK(c, eval_set_lds(lds));
     const int nb = eval_blocks(c, lds);
-    int parity = 0;
     int* h_active = (int*)c->pinned.p;
     int active = B;
-    for (int step = 0; step < kMaxSteps && active > 0; ++step) {
-        tm.begin();
-        HIPCHK(c, launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                              c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[parity],
-                              &q[1 - parity], c->part.as<Part>(), sp.HS, nullptr));
-        tm.end(0);
-        tm.begin();
-        HIPCHK(c, launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
-                                  c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(),
-                                  c->hyps.as<Hyp>(), c->part.as<Part>(), c->items.as<Item>(),
-                                  &q[1 - parity], c->n_active.as<int>()));
-        tm.end(1);
-        parity = 1 - parity;
-        if ((step & 3) == 3) {
-            HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-            HIPCHK(c, hipStreamSynchronize(c->stream));
-            active = B + *h_active;  // n_active counts finished windows down from zero
+    auto step_pair = [&](bool timed) -> hipError_t {
+        // two steps: parity 0 then 1, so the queue pair is back in place
+        for (int parity = 0; parity < 2; ++parity) {
+            if (timed) tm.begin();
+            hipError_t e = launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[parity],
+                                       &q[1 - parity], c->part.as<Part>(), sp.HS, nullptr);
+            if (e != hipSuccess) return e;
+            if (timed) tm.end(0);
+            if (timed) tm.begin();
+            e = launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
+                                c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(), c->hyps.as<Hyp>(),
+                                c->part.as<Part>(), c->items.as<Item>(), &q[1 - parity], c->n_active.as<int>());
+            if (e != hipSuccess) return e;
+            if (timed) tm.end(1);
         }
+        return hipSuccess;
+    };
+    const bool graph = c->tune.graph && !c->profiling;
+    if (graph) {
+        // the captured pair depends on every pointer and by-value argument
+        std::vector<unsigned char> key;
+        auto put = [&](const void* p, size_t n) {
+            const unsigned char* b = (const unsigned char*)p;
+            key.insert(key.end(), b, b + n);
+        };
+        void* ptrs[] = {c->ev.p, c->seg_off.p, c->seg_own.p, c->hyps.p, c->items.p, c->queues.p, c->part.p,
+                        c->wp.p, c->state.p, c->front.p, c->sel.p, c->n_active.p, (void*)c->stream};
+        put(ptrs, sizeof ptrs);
+        put(&g, sizeof g);
+        put(&sp, sizeof sp);
+        int ints[] = {B, T, nb, (int)lds};
+        put(ints, sizeof ints);
+        if (!c->gexec || key != c->gkey) {
+            if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+            hipGraph_t gr = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = step_pair(false);
+            hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+            HIPCHK(c, e1);
+            HIPCHK(c, e2);
+            hipError_t e3 = hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            HIPCHK(c, e3);
+            c->gkey = key;
+        }
+    }
+    for (int step = 0; step < kMaxSteps && active > 0; step += 4) {
+        if (graph) {
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+        } else {
+            HIPCHK(c, step_pair(true));
+            HIPCHK(c, step_pair(true));
+        }
+        HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        active = B + *h_active;  // n_active counts finished windows down from zero
     }
     std::vector<WinState> hs(B);
     HIPCHK(c, hipMemcpyAsync(hs.data(), c->state.p, sizeof(WinState) * B, hipMemcpyDeviceToHost, c->stream));
@@ -523,6 +570,15 @@ int ecmd_ctx_create(ecmd_ctx** out, int device, void* hip_stream) {
     if (!c) return ECMD_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    if (!c->stream) {
+        // a blocking stream of default priority: ordered with the null stream,
+        // and capturable into a graph
+        if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+            delete c;
+            return ECMD_EDEVICE;
+        }
+        c->stream = c->own_stream;
+    }
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
     *out = c;
@@ -540,10 +596,75 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
     for (DevBuf* b : bufs) b->release();
     c->pinned.release();
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }
 
 const char* ecmd_last_error(const ecmd_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int ecmd_ctx_set_tuning(ecmd_ctx* c, const ecmd_tuning* t) {
+    if (!c || !t) return ECMD_EINVAL;
+    if (t->frontier_batch < 0 || t->frontier_batch > 1024 || t->tile_px < 0)
+        return fail(c, ECMD_EINVAL, "tuning out of range");
+    c->tune = *t;
+    return ECMD_OK;
+}
+
+int ecmd_ctx_get_tuning(const ecmd_ctx* c, ecmd_tuning* out) {
+    if (!c || !out) return ECMD_EINVAL;
+    *out = c->tune;
+    return ECMD_OK;
+}
+
+int ecmd_autotune(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                  const int64_t* offsets, const float* tau, int32_t B, const ecmd_search* search, uint32_t flags,
+                  ecmd_tuning* best, double* ms_best) {
+    if (!c || !search || !best) return ECMD_EINVAL;
+    if (B <= 0) return fail(c, ECMD_EINVAL, "autotune needs windows");
+    ecmd_search s = *search;
+    s.frontier_batch = 0;
+    const ecmd_tuning saved = c->tune;
+    const bool prof = c->profiling;
+    c->profiling = false;
+    std::vector<ecmd_result> out(B);
+    const int full = tile_budget(c);
+    const int Fs[] = {16, 32, 64, 128, 256};
+    const int tiles[] = {full, full / 2, full / 4};
+    double best_ms = 1e300;
+    ecmd_tuning bt = saved;
+    for (int ti = 0; ti < 3; ++ti) {
+        if (ti > 0 && (long long)sensor->width * sensor->height <= tiles[ti]) break;  // one tile already
+        for (int F : Fs) {
+            for (int gr = 0; gr < 2; ++gr) {
+                c->tune.frontier_batch = F;
+                c->tune.tile_px = ti == 0 ? 0 : tiles[ti];
+                c->tune.graph = gr;
+                double ms = 1e300;
+                for (int rep = 0; rep < 3; ++rep) {
+                    auto t0 = std::chrono::steady_clock::now();
+                    int rc = batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, &s, flags, nullptr, out.data());
+                    auto t1 = std::chrono::steady_clock::now();
+                    if (rc < 0 && rc != ECMD_EBUDGET && rc != ECMD_EFRONTIER) {
+                        c->tune = saved;
+                        c->profiling = prof;
+                        return rc;
+                    }
+                    if (rep > 0) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    bt = c->tune;
+                }
+            }
+        }
+    }
+    c->tune = bt;
+    c->profiling = prof;
+    *best = bt;
+    if (ms_best) *ms_best = best_ms;
+    return ECMD_OK;
+}
 
 int ecmd_ctx_set_profiling(ecmd_ctx* c, int enable) {
     if (!c) return ECMD_EINVAL;

@@ -64,7 +64,7 @@ struct Geometry {
 struct WinParam {
     float tau;
     float r_lo, r_hi;  // rates at d_lo and d_hi
-    int pad;
+    float kscale;      // walk-length classes per unit of |ax| + |ay|
     long long n_events;
 };
 
@@ -109,15 +109,16 @@ struct Queue {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return the launch status.
 
-hipError_t launch_winparam(hipStream_t s, const float* tau, const long long* offsets, int B,
-                           float d_lo, float d_hi, WinParam* wp);
-// phase 0: count events per (window, tile) and scan into segments;
-// phase 1: scatter the events into their segments.
+hipError_t launch_winparam(hipStream_t s, const Geometry& g, const float* tau, const long long* offsets,
+                           int B, float d_lo, float d_hi, WinParam* wp);
+// Counters of the prep (per window, tile, owned/guest and walk class).
+size_t prep_counters(int B, int T);
+// phase 0: count events per (window, tile, owned/guest, walk class) and scan
+// into segments; phase 1: scatter the events into their segments.
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
                        const float* t_rel, const long long* offsets, const WinParam* wp, int B,
-                       const int* blk_start, int nblk, int chunk, int* cnt_own, int* cnt_guest,
-                       long long* seg_off, int* seg_own, unsigned long long* cursor, float4* ev,
-                       int* err_flag);
+                       const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
+                       unsigned long long* cursor, float4* ev, int* err_flag);
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, Item* items, Queue* q, int T,
                        const long long* seg_off);

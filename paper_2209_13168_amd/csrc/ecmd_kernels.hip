@@ -71,23 +71,30 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // ------------------------------------------------------------ window params
 
+// Walk-length classes: inside a tile segment, events are ordered by
+// |ax| + |ay| (longest first).  For any interval an event's staircase walk
+// is about (|ax| + |ay|)(r_b - r_a) pixels long, so neighbouring lanes of a
+// wave then walk similar distances.
+constexpr int kNB = 16;
+
 __global__ void k_winparam(const float* __restrict__ tau, const long long* __restrict__ offsets, int B,
-                           float d_lo, float d_hi, WinParam* __restrict__ wp) {
+                           float d_lo, float d_hi, int W, int H, float cx, float cy, WinParam* __restrict__ wp) {
     int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= B) return;
     WinParam p;
     p.tau = tau[w];
     p.r_lo = rate_of(d_lo, p.tau);
     p.r_hi = rate_of(d_hi, p.tau);
-    p.pad = 0;
+    const float key_max = (fmaxf(fabsf(cx), fabsf((float)W - cx)) + fmaxf(fabsf(cy), fabsf((float)H - cy))) * p.tau;
+    p.kscale = key_max > 0.0f ? (float)kNB / key_max : 0.0f;
     p.n_events = offsets[w + 1] - offsets[w];
     wp[w] = p;
 }
 
-hipError_t launch_winparam(hipStream_t s, const float* tau, const long long* offsets, int B,
+hipError_t launch_winparam(hipStream_t s, const Geometry& g, const float* tau, const long long* offsets, int B,
                            float d_lo, float d_hi, WinParam* wp) {
     if (B <= 0) return hipSuccess;
-    k_winparam<<<(B + 255) / 256, 256, 0, s>>>(tau, offsets, B, d_lo, d_hi, wp);
+    k_winparam<<<(B + 255) / 256, 256, 0, s>>>(tau, offsets, B, d_lo, d_hi, g.W, g.H, g.cx, g.cy, wp);
     return hipGetLastError();
 }
 
@@ -127,16 +134,46 @@ __device__ __forceinline__ bool event_tiles(const Geometry& g, float x, float y,
     return true;
 }
 
+__device__ __forceinline__ int walk_class(float ax, float ay, float kscale) {
+    int b = (int)((fabsf(ax) + fabsf(ay)) * kscale);
+    return kNB - 1 - min(max(b, 0), kNB - 1);
+}
+
+// counter of (tile, owned 0 / guest 1, walk class) inside a window
+__device__ __forceinline__ int ctr_of(int t, int og, int b) { return (t * 2 + og) * kNB + b; }
+
 constexpr int kPrepThreads = 256;
+constexpr int kCtr = kMaxTiles * 2 * kNB;
+
+// Per-event prep: validity, (ax, ay), reachable tiles and walk class.
+struct PrepEv {
+    bool ok, valid;
+    float x, y, ax, ay;
+    int tx0, tx1, ty0, ty1, cls;
+};
+
+__device__ __forceinline__ PrepEv prep_event(const Geometry& g, const WinParam& p, float xv, float yv, float tv) {
+    PrepEv e;
+    e.valid = isfinite(xv) && isfinite(yv) && tv >= 0.0f && tv <= p.tau;
+    e.ok = false;
+    if (!e.valid) return e;
+    const float ux = xv - g.cx, uy = yv - g.cy, delta = p.tau - tv;
+    e.x = xv;
+    e.y = yv;
+    e.ax = ux * delta;
+    e.ay = uy * delta;
+    e.ok = event_tiles(g, xv, yv, e.ax, e.ay, p.r_lo, p.r_hi, e.tx0, e.tx1, e.ty0, e.ty1);
+    e.cls = walk_class(e.ax, e.ay, p.kscale);
+    return e;
+}
 
 __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     Geometry g, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ t_rel,
     const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
-    const int* __restrict__ blk_start, int chunk, int* __restrict__ cnt_own, int* __restrict__ cnt_guest,
-    int* __restrict__ err_flag) {
-    __shared__ int s_own[kMaxTiles], s_guest[kMaxTiles];
-    const int T = g.T;
-    for (int t = threadIdx.x; t < T; t += blockDim.x) { s_own[t] = 0; s_guest[t] = 0; }
+    const int* __restrict__ blk_start, int chunk, int* __restrict__ cnt, int* __restrict__ err_flag) {
+    __shared__ int s_cnt[kCtr];
+    const int nc = g.T * 2 * kNB;
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
     __syncthreads();
     const int w = window_of_block(blk_start, B, blockIdx.x);
     const int c = blockIdx.x - blk_start[w];
@@ -144,40 +181,32 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     const long long end = min(beg + chunk, offsets[w + 1]);
     const WinParam p = wp[w];
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        float xv = x[i], yv = y[i], tv = t_rel[i];
-        if (!(isfinite(xv) && isfinite(yv) && tv >= 0.0f && tv <= p.tau)) {
-            atomicOr(err_flag, 1);
-            continue;
-        }
-        float ux = xv - g.cx, uy = yv - g.cy, delta = p.tau - tv;
-        float ax = ux * delta, ay = uy * delta;
-        int tx0, tx1, ty0, ty1;
-        if (!event_tiles(g, xv, yv, ax, ay, p.r_lo, p.r_hi, tx0, tx1, ty0, ty1)) continue;
-        atomicAdd(&s_own[ty0 * g.ntx + tx0], 1);
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx)
-                if (ty != ty0 || tx != tx0) atomicAdd(&s_guest[ty * g.ntx + tx], 1);
+        const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
+        if (!e.valid) atomicOr(err_flag, 1);
+        if (!e.ok) continue;
+        for (int ty = e.ty0; ty <= e.ty1; ++ty)
+            for (int tx = e.tx0; tx <= e.tx1; ++tx)
+                atomicAdd(&s_cnt[ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        if (s_own[t]) atomicAdd(&cnt_own[w * T + t], s_own[t]);
-        if (s_guest[t]) atomicAdd(&cnt_guest[w * T + t], s_guest[t]);
-    }
+    for (int k = threadIdx.x; k < nc; k += blockDim.x)
+        if (s_cnt[k]) atomicAdd(&cnt[(long long)w * nc + k], s_cnt[k]);
 }
 
-// Exclusive scan of segment sizes (one workgroup).
-__global__ __launch_bounds__(1024) void k_prep_scan(int nseg, const int* __restrict__ cnt_own,
-                                                    const int* __restrict__ cnt_guest,
-                                                    long long* __restrict__ seg_off,
-                                                    int* __restrict__ seg_own,
+// Exclusive scan of the counters of every (window, tile, owned/guest,
+// class) in that order (one workgroup); then the segment of (w, t) starts
+// at its first counter and its owned events end where its guests begin.
+__global__ __launch_bounds__(1024) void k_prep_scan(int B, int T, const int* __restrict__ cnt,
+                                                    long long* __restrict__ seg_off, int* __restrict__ seg_own,
                                                     unsigned long long* __restrict__ cursor) {
     __shared__ long long s[1024];
     __shared__ long long carry;
+    const long long n = (long long)B * T * 2 * kNB;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < nseg; base += 1024) {
-        int k = base + threadIdx.x;
-        long long v = k < nseg ? (long long)cnt_own[k] + cnt_guest[k] : 0;
+    for (long long base = 0; base < n; base += 1024) {
+        const long long k = base + threadIdx.x;
+        const long long v = k < n ? cnt[k] : 0;
         s[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
@@ -186,19 +215,19 @@ __global__ __launch_bounds__(1024) void k_prep_scan(int nseg, const int* __restr
             s[threadIdx.x] += a;
             __syncthreads();
         }
-        long long incl = s[threadIdx.x] + carry;
-        if (k < nseg) {
-            long long off = incl - v;
-            seg_off[k] = off;
-            seg_own[k] = cnt_own[k];
-            cursor[2 * k] = (unsigned long long)off;
-            cursor[2 * k + 1] = (unsigned long long)(off + cnt_own[k]);
-        }
+        const long long incl = s[threadIdx.x] + carry;
+        if (k < n) cursor[k] = (unsigned long long)(incl - v);
         __syncthreads();
         if (threadIdx.x == 1023) carry = incl;
         __syncthreads();
     }
-    if (threadIdx.x == 0) seg_off[nseg] = carry;
+    for (int st = threadIdx.x; st < B * T; st += 1024) {
+        const long long o0 = (long long)cursor[(long long)st * 2 * kNB];
+        const long long o1 = (long long)cursor[(long long)st * 2 * kNB + kNB];
+        seg_off[st] = o0;
+        seg_own[st] = (int)(o1 - o0);
+    }
+    if (threadIdx.x == 0) seg_off[(long long)B * T] = carry;
 }
 
 __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
@@ -206,71 +235,61 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, unsigned long long* __restrict__ cursor,
     float4* __restrict__ ev) {
-    __shared__ int s_cnt[2 * kMaxTiles];
-    __shared__ unsigned long long s_base[2 * kMaxTiles];
-    const int T = g.T;
-    for (int t = threadIdx.x; t < 2 * T; t += blockDim.x) s_cnt[t] = 0;
+    __shared__ int s_cnt[kCtr];
+    __shared__ unsigned long long s_base[kCtr];
+    const int nc = g.T * 2 * kNB;
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
     __syncthreads();
     const int w = window_of_block(blk_start, B, blockIdx.x);
     const int c = blockIdx.x - blk_start[w];
     const long long beg = offsets[w] + (long long)c * chunk;
     const long long end = min(beg + chunk, offsets[w + 1]);
     const WinParam p = wp[w];
-    // pass 1: count per (tile, owned/guest) within the block
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        float xv = x[i], yv = y[i], tv = t_rel[i];
-        if (!(isfinite(xv) && isfinite(yv) && tv >= 0.0f && tv <= p.tau)) continue;
-        float ax = (xv - g.cx) * (p.tau - tv), ay = (yv - g.cy) * (p.tau - tv);
-        int tx0, tx1, ty0, ty1;
-        if (!event_tiles(g, xv, yv, ax, ay, p.r_lo, p.r_hi, tx0, tx1, ty0, ty1)) continue;
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                int own = (ty == ty0 && tx == tx0) ? 0 : 1;
-                atomicAdd(&s_cnt[2 * (ty * g.ntx + tx) + own], 1);
-            }
+        const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
+        if (!e.ok) continue;
+        for (int ty = e.ty0; ty <= e.ty1; ++ty)
+            for (int tx = e.tx0; tx <= e.tx1; ++tx)
+                atomicAdd(&s_cnt[ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < 2 * T; k += blockDim.x) {
-        int n = s_cnt[k];
-        s_base[k] = n ? atomicAdd(&cursor[2 * (w * T) + k], (unsigned long long)n) : 0ull;
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+        const int n = s_cnt[k];
+        s_base[k] = n ? atomicAdd(&cursor[(long long)w * nc + k], (unsigned long long)n) : 0ull;
         s_cnt[k] = 0;
     }
     __syncthreads();
-    // pass 2: write
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        float xv = x[i], yv = y[i], tv = t_rel[i];
-        if (!(isfinite(xv) && isfinite(yv) && tv >= 0.0f && tv <= p.tau)) continue;
-        float ax = (xv - g.cx) * (p.tau - tv), ay = (yv - g.cy) * (p.tau - tv);
-        int tx0, tx1, ty0, ty1;
-        if (!event_tiles(g, xv, yv, ax, ay, p.r_lo, p.r_hi, tx0, tx1, ty0, ty1)) continue;
-        float4 e = make_float4(xv, yv, ax, ay);
-        for (int ty = ty0; ty <= ty1; ++ty)
-            for (int tx = tx0; tx <= tx1; ++tx) {
-                int k = 2 * (ty * g.ntx + tx) + ((ty == ty0 && tx == tx0) ? 0 : 1);
-                int r = atomicAdd(&s_cnt[k], 1);
-                ev[s_base[k] + (unsigned long long)r] = e;
+        const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
+        if (!e.ok) continue;
+        const float4 v = make_float4(e.x, e.y, e.ax, e.ay);
+        for (int ty = e.ty0; ty <= e.ty1; ++ty)
+            for (int tx = e.tx0; tx <= e.tx1; ++tx) {
+                const int k = ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls);
+                const int r = atomicAdd(&s_cnt[k], 1);
+                ev[s_base[k] + (unsigned long long)r] = v;
             }
     }
 }
 
+size_t prep_counters(int B, int T) { return (size_t)B * T * 2 * kNB; }
+
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
                        const float* t_rel, const long long* offsets, const WinParam* wp, int B,
-                       const int* blk_start, int nblk, int chunk, int* cnt_own, int* cnt_guest,
-                       long long* seg_off, int* seg_own, unsigned long long* cursor, float4* ev,
-                       int* err_flag) {
+                       const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
+                       unsigned long long* cursor, float4* ev, int* err_flag) {
     if (phase == 0) {
         if (nblk > 0) {
-            k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk,
-                                                       cnt_own, cnt_guest, err_flag);
+            k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk, cnt,
+                                                       err_flag);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
-        k_prep_scan<<<1, 1024, 0, s>>>(B * g.T, cnt_own, cnt_guest, seg_off, seg_own, cursor);
+        k_prep_scan<<<1, 1024, 0, s>>>(B, g.T, cnt, seg_off, seg_own, cursor);
         return hipGetLastError();
     }
     if (nblk > 0) {
-        k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk,
-                                                     cursor, ev);
+        k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk, cursor, ev);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -279,51 +298,44 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // ------------------------------------------------------------ evaluation (a2, a3)
 
 // Add one to every pixel of this tile that the staircase walk from pixel
-// (kxa, kya) to pixel (kxb, kyb) visits (eq. (17)).  Corner decisions follow
-// the event's ray through (x, y) with direction (ax, ay), in fp64; within
-// 2^-8 px of a corner both side pixels are counted.  Pixels outside the
-// tile increment the thread's private spill word `spill` instead, whose
-// returned counts are removed at the end (see k_eval).
+// (kx, ky) to pixel (kxb, kyb) visits (eq. (17)); the start pixel is
+// counted by the caller.  Corner decisions follow the event's ray through
+// (x, y) with direction (ax, ay), in fp64: e = |X - x||ay| - |Y - y||ax|
+// compares where the ray meets the next vertical and horizontal pixel
+// edges; within 2^-8 px of the corner both side pixels are counted.  The
+// increments do not return values (the sum of squares comes from one pass
+// over the tile afterwards); pixels outside the tile go to the thread's
+// private spill word `spill`.
+__device__ __forceinline__ void tile_add(unsigned* __restrict__ tile, unsigned spill, int x0, int y0, unsigned tw,
+                                         unsigned th, int px, int py) {
+    const unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
+    const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
+    __hip_atomic_fetch_add(&tile[a], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned spill, int x0, int y0,
-                                          unsigned tw, unsigned th, int kxa, int kya, int kxb, int kyb,
-                                          double x, double y, double ax, double ay,
-                                          unsigned long long& sumold, unsigned& visits) {
-    const int sx = (kxb > kxa) - (kxb < kxa);
-    const int sy = (kyb > kya) - (kyb < kya);
-    const double thr = (fabs(ax) + fabs(ay)) * 0.00390625;
-    const double aax = fabs(ax), aay = fabs(ay);
-    int kx = kxa, ky = kya;
-    auto visit = [&](int px, int py) {
-        const unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
-        const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
-        sumold += atomicAdd(&tile[a], 1u);
-        visits += 1;
-    };
-    visit(kx, ky);
-    while (kx != kxb || ky != kyb) {
-        if (kx == kxb) {
-            ky += sy;
-        } else if (ky == kyb) {
-            kx += sx;
-        } else {
-            double X = (double)(kx + (sx > 0));
-            double Y = (double)(ky + (sy > 0));
-            double ex = fabs(X - x) * aay;
-            double ey = fabs(Y - y) * aax;
-            double e = ex - ey;
-            if (e < -thr) {
-                kx += sx;
-            } else if (e > thr) {
-                ky += sy;
-            } else {
-                visit(kx + sx, ky);
-                visit(kx, ky + sy);
-                kx += sx;
-                ky += sy;
-            }
+                                          unsigned tw, unsigned th, int kx, int ky, int kxb, int kyb,
+                                          float xf, float yf, float axf, float ayf) {
+    const int sx = (kxb > kx) - (kxb < kx);
+    const int sy = (kyb > ky) - (kyb < ky);
+    const double x = (double)xf, y = (double)yf;
+    const double aax = fabs((double)axf), aay = fabs((double)ayf);
+    const double thr = (aax + aay) * 0.00390625;
+    const int cx1 = sx > 0, cy1 = sy > 0;
+    do {
+        const bool dx = kx != kxb, dy = ky != kyb;
+        const double ex = fabs((double)(kx + cx1) - x) * aay;
+        const double ey = fabs((double)(ky + cy1) - y) * aax;
+        const double e = ex - ey;
+        const bool lo = e < -thr, hi = e > thr;
+        if (dx && dy && !lo && !hi) {  // the ray passes near the corner: both side pixels
+            tile_add(tile, spill, x0, y0, tw, th, kx + sx, ky);
+            tile_add(tile, spill, x0, y0, tw, th, kx, ky + sy);
         }
-        visit(kx, ky);
-    }
+        kx += (dx && (!dy || !hi)) ? sx : 0;
+        ky += (dy && (!dx || !lo)) ? sy : 0;
+        tile_add(tile, spill, x0, y0, tw, th, kx, ky);
+    } while (kx != kxb || ky != kyb);
 }
 
 // LDS layout of k_eval: [tile: tw*th counters][spill: one word per thread]
@@ -377,7 +389,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         for (int i = tid; i < npx + kEvalThreads; i += kEvalThreads) tile[i] = 0u;
         __syncthreads();
 
-        unsigned long long sumold = 0, nlow = 0;
+        unsigned long long sumold = 0, nlow = 0, nlow_sq = 0, nlow_cnt = 0;
         unsigned visits = 0;
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
@@ -423,23 +435,46 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
                 if (i < own_end && inside(xa, ya, Wf, Hf) && inside(xb, yb, Wf, Hf)) nlow += 1;
-                walk_tile(tile, spill, x0, y0, tw, th, flr_clamp(xa, g.W), flr_clamp(ya, g.H),
-                          flr_clamp(xb, g.W), flr_clamp(yb, g.H), (double)e.x, (double)e.y, (double)e.z,
-                          (double)e.w, sumold, visits);
+                const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
+                const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
+                tile_add(tile, spill, x0, y0, tw, th, kxa, kya);
+                if (kxa != kxb || kya != kyb)
+                    walk_tile(tile, spill, x0, y0, tw, th, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
                 e = en;
             }
+            // S_bar and the increment count from one pass over the tile
+            __syncthreads();
+            unsigned long long sq = 0, cnt = 0;
+            for (int k = tid; k < npx; k += kEvalThreads) {
+                const unsigned long long h = tile[k];
+                sq += h * h;
+                cnt += h;
+            }
+            sumold = 0;
+            visits = 0;
+            nlow_sq = sq;
+            nlow_cnt = cnt;
         }
-        // Remove the spill word: its m increments returned 0, 1, .., m-1.
-        const unsigned m = tile[spill];
-        sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
-        unsigned long long hits = (unsigned long long)(visits - m);
-        // block reduction of (sumold, hits, nlow)
-        sumold = wave_sum(sumold);
+        // Point items: remove the spill word, whose m increments returned
+        // 0, 1, .., m-1; then S = sum(2*old + 1) over the in-tile events.
+        // Interval items: S_bar = sum H_bar^2 and the count from the pass.
+        unsigned long long sq, hits;
+        if (hp.kind == HYP_POINT) {
+            const unsigned m = tile[spill];
+            sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
+            hits = (unsigned long long)(visits - m);
+            sq = 2ull * sumold + hits;
+        } else {
+            sq = nlow_sq;
+            hits = nlow_cnt;
+        }
+        // block reduction of (S, hits, nlow)
+        sq = wave_sum(sq);
         hits = wave_sum(hits);
         nlow = wave_sum(nlow);
         const int wave = tid >> 6, lane = tid & 63;
         if (lane == 0) {
-            s_red[wave] = sumold;
+            s_red[wave] = sq;
             s_red[kEvalWaves + wave] = hits;
             s_red[2 * kEvalWaves + wave] = nlow;
         }
@@ -452,7 +487,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 c += s_red[2 * kEvalWaves + k];
             }
             Part pt;
-            pt.S = 2ull * a + b;
+            pt.S = a;
             pt.N = (long long)(hp.kind == HYP_POINT ? b : c);
             pt.U = b;
             pt.pad = 0;
@@ -486,21 +521,77 @@ hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds
 
 // ------------------------------------------------------------ frontier (a4)
 
-// Hypothesis slots of the selected nodes and the work items for them.
-__device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const long long* seg_off,
-                          const Sel* sl, int n_sel, Hyp* hy, Item* items, Queue* qf) {
-    const int F = sp.F, HS = sp.HS;
-    __shared__ int s_n_nonempty, s_base;
-    __shared__ int s_tiles[kMaxTiles];
-    __shared__ int s_active[3 * 1024];  // slots with work (HS <= 3 * 1024)
-    __shared__ int s_nact;
-    if (threadIdx.x == 0) { s_n_nonempty = 0; s_nact = 0; }
-    __syncthreads();
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        long long seg = (long long)w * T + t;
-        if (seg_off[seg + 1] > seg_off[seg]) s_tiles[atomicAdd(&s_n_nonempty, 1)] = t;
+constexpr int NTF = kFrontThreads;
+constexpr int NWF = NTF / 64;
+
+// Exclusive prefix sum of v over the workgroup (in thread order); `total`
+// receives the sum.  All threads must call it.
+__device__ __forceinline__ int block_scan(int v, int* s_wave, int& total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    for (int h = threadIdx.x; h < HS; h += blockDim.x) {
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int k = 0; k < NWF; ++k) {
+        const int t = s_wave[k];
+        if (k < wave) base += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return base + x - v;
+}
+
+// Lexicographic maximum of (K, -j) over the workgroup.
+__device__ __forceinline__ void block_argmax(i128& K, unsigned& j, long long* s_hi, unsigned long long* s_lo,
+                                             unsigned* s_j) {
+    const int tid = threadIdx.x;
+    sp128(K, s_hi[tid], s_lo[tid]);
+    s_j[tid] = j;
+    __syncthreads();
+    for (int o = NTF / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            const i128 a = mk128(s_hi[tid], s_lo[tid]), b = mk128(s_hi[tid + o], s_lo[tid + o]);
+            const unsigned ja = s_j[tid], jb = s_j[tid + o];
+            if (b > a || (b == a && jb < ja)) {
+                s_hi[tid] = s_hi[tid + o];
+                s_lo[tid] = s_lo[tid + o];
+                s_j[tid] = jb;
+            }
+        }
+        __syncthreads();
+    }
+    K = mk128(s_hi[0], s_lo[0]);
+    j = s_j[0];
+    __syncthreads();
+}
+
+// Sum of the tiles' partial sums of one hypothesis slot.
+__device__ __forceinline__ void slot_sums(const Part* pw, int slot, int T, const int* tiles, int nt,
+                                          unsigned long long& S, long long& N, unsigned long long& U) {
+    S = 0;
+    N = 0;
+    U = 0;
+    for (int k = 0; k < nt; ++k) {
+        const Part q = pw[(long long)slot * T + tiles[k]];
+        S += q.S;
+        N += q.N;
+        U += q.U;
+    }
+}
+
+// Hypotheses of the selected nodes and their work items.
+__device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
+                          const Sel* sl, int n_sel, Hyp* hy, Item* items, Queue* qf, int* s_wave) {
+    const int F = sp.F, HS = sp.HS;
+    __shared__ int s_base;
+    // slots with work: points [0, n_sel), intervals F + [0, 2 n_sel) of nodes with children
+    for (int h0 = 0; h0 < HS; h0 += NTF) {
+        const int h = h0 + threadIdx.x;
         Hyp hp;
         hp.kind = HYP_NONE;
         hp.pad = 0;
@@ -510,42 +601,57 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
                 hp.kind = HYP_POINT;
                 hp.ra = hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, sl[h].jc), p.tau);
             }
-        } else {
-            int c = h - F, i = c >> 1;
+        } else if (h < HS) {
+            const int c = h - F, i = c >> 1;
             if (i < n_sel && sl[i].kids) {
-                unsigned a = (c & 1) ? sl[i].jc : sl[i].ja;
-                unsigned b = (c & 1) ? sl[i].jb : sl[i].jc;
+                const unsigned a = (c & 1) ? sl[i].jc : sl[i].ja;
+                const unsigned b = (c & 1) ? sl[i].jb : sl[i].jc;
                 hp.kind = HYP_INTERVAL;
                 hp.ra = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, a), p.tau);
                 hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, b), p.tau);
             }
         }
-        hy[h] = hp;
-        if (hp.kind != HYP_NONE) s_active[atomicAdd(&s_nact, 1)] = h;
+        if (h < HS) hy[h] = hp;
+        int tot;
+        const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
+        if (threadIdx.x == 0) s_base = (tot * nt) ? atomicAdd(&qf->n_items, tot * nt) : 0;
+        __syncthreads();
+        if (hp.kind != HYP_NONE)
+            for (int k = 0; k < nt; ++k) {
+                Item it;
+                it.wh = w * HS + h;
+                it.t = tiles[k];
+                items[s_base + r * nt + k] = it;
+            }
+        __syncthreads();
     }
-    __syncthreads();
-    const int nt = s_n_nonempty, na = s_nact;
-    if (threadIdx.x == 0) s_base = (na * nt) ? atomicAdd(&qf->n_items, na * nt) : 0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < na * nt; k += blockDim.x) {
-        Item it;
-        it.wh = w * HS + s_active[k / nt];
-        it.t = s_tiles[k % nt];
-        items[s_base + k] = it;
+}
+
+__device__ __forceinline__ void nonempty_tiles(int w, int T, const long long* seg_off, int* tiles, int* s_nt,
+                                               int* s_wave) {
+    const int t = threadIdx.x;
+    int ne = 0;
+    if (t < T) {
+        const long long seg = (long long)w * T + t;
+        ne = seg_off[seg + 1] > seg_off[seg] ? 1 : 0;
     }
+    int tot;
+    const int r = block_scan(ne, s_wave, tot);
+    if (ne) tiles[r] = t;
+    if (threadIdx.x == 0) *s_nt = tot;
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kFrontThreads) void k_init(Search sp, const WinParam* __restrict__ wp,
-                                                        const float* __restrict__ seeds, int B,
-                                                        WinState* __restrict__ st, Sel* __restrict__ sel,
-                                                        Hyp* __restrict__ hyps, Item* __restrict__ items,
-                                                        Queue* __restrict__ q, int T,
-                                                        const long long* __restrict__ seg_off) {
+__global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restrict__ wp,
+                                              const float* __restrict__ seeds, int B, WinState* __restrict__ st,
+                                              Sel* __restrict__ sel, Hyp* __restrict__ hyps,
+                                              Item* __restrict__ items, Queue* __restrict__ q, int T,
+                                              const long long* __restrict__ seg_off) {
     const int w = blockIdx.x;
     const unsigned top = 1u << sp.L;
     Sel* sl = sel + (long long)w * sp.F;
-    __shared__ int s_nsel;
+    __shared__ int s_nsel, s_nt, s_wave[NWF];
+    __shared__ int s_tiles[kMaxTiles];
     if (threadIdx.x == 0) {
         WinState s = WinState{};
         s.Kinc_hi = -1;
@@ -560,10 +666,10 @@ __global__ __launch_bounds__(kFrontThreads) void k_init(Search sp, const WinPara
         sl[0] = root;
         int n_sel = 1;
         if (seeds) {
-            float d = seeds[w];
+            const float d = seeds[w];
             if (isfinite(d)) {
-                double span = (double)sp.d_hi - (double)sp.d_lo;
-                double v = ((double)d - (double)sp.d_lo) / span * (double)top;
+                const double span = (double)sp.d_hi - (double)sp.d_lo;
+                const double v = ((double)d - (double)sp.d_lo) / span * (double)top;
                 long long j = llround(v);
                 j = j < 1 ? 1 : (j > (long long)top - 1 ? (long long)top - 1 : j);
                 if ((unsigned)j != root.jc && sp.F > 1) {
@@ -582,33 +688,38 @@ __global__ __launch_bounds__(kFrontThreads) void k_init(Search sp, const WinPara
         s_nsel = n_sel;
     }
     __syncthreads();
-    emit_hyps(sp, wp[w], w, T, seg_off, sl, s_nsel, hyps + (long long)w * sp.HS, items, q);
+    nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
+    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, items, q, s_wave);
 }
 
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, Item* items, Queue* q, int T,
                        const long long* seg_off) {
     if (B <= 0) return hipSuccess;
-    k_init<<<B, kFrontThreads, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, items, q, T, seg_off);
+    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, items, q, T, seg_off);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kFrontThreads) void k_frontier(
+// One step of Algorithm 1 for window blockIdx.x: absorb the evaluated
+// hypotheses, update the incumbent, queue the improvable children, drop
+// queued nodes that can no longer improve, decide whether to stop, select
+// the next nodes, emit their hypotheses.  Every order below is the array
+// order (scans, no atomic slot races), so the search is reproducible.
+__global__ __launch_bounds__(NTF) void k_frontier(
     Search sp, const WinParam* __restrict__ wp, int B, int T, const long long* __restrict__ seg_off,
     WinState* __restrict__ st, Node* __restrict__ front, Sel* __restrict__ sel, Hyp* __restrict__ hyps,
     const Part* __restrict__ part, Item* __restrict__ items, Queue* __restrict__ qf,
     int* __restrict__ n_active) {
     const int w = blockIdx.x, tid = threadIdx.x;
-    constexpr int NT = kFrontThreads;
     __shared__ WinState s;
-    __shared__ long long s_khi[NT];
-    __shared__ unsigned long long s_klo[NT];
-    __shared__ unsigned s_j[NT];
-    __shared__ int s_cnt, s_overflow, s_hist[130], s_quota_ctr, s_nsel_new, s_kids_new, s_out;
+    __shared__ long long s_hi[NTF];
+    __shared__ unsigned long long s_lo[NTF];
+    __shared__ unsigned s_j[NTF];
+    __shared__ int s_wave[NWF], s_tiles[kMaxTiles], s_nt;
+    __shared__ int s_hist[130];
+    __shared__ int s_bstar, s_quota, s_stop, s_take;
     __shared__ unsigned long long s_pix;
-    __shared__ long long s_pruned, s_nbound;
-    __shared__ int s_scan[NT];
-    __shared__ int s_bstar, s_quota, s_stop;
+    __shared__ long long s_nbound, s_pruned;
     if (tid == 0) s = st[w];
     __syncthreads();
     if (!s.active) return;
@@ -618,125 +729,89 @@ __global__ __launch_bounds__(kFrontThreads) void k_frontier(
     Node* fr = front + (long long)w * CAP;
     Sel* sl = sel + (long long)w * F;
     const Part* pw = part + (long long)w * HS * T;
-    const long long* so = seg_off + (long long)w * T;
+    nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
+    const int nt = s_nt;
+    const int n_sel = s.n_sel;
 
     // (1) centre points: lexicographic max of (K, -j) with the incumbent
     i128 bK = mk128(s.Kinc_hi, s.Kinc_lo);
     unsigned bJ = s.j_inc;
-    for (int i = tid; i < s.n_sel; i += NT) {
-        unsigned long long S = 0;
-        long long N = 0;
-        for (int t = 0; t < T; ++t) {
-            if (so[t + 1] > so[t]) {
-                S += pw[(long long)i * T + t].S;
-                N += pw[(long long)i * T + t].N;
-            }
-        }
-        i128 K = (i128)M * (i128)S - (i128)N * (i128)N;
-        unsigned jc = sl[i].jc;
+    for (int i = tid; i < n_sel; i += NTF) {
+        unsigned long long S, U;
+        long long N;
+        slot_sums(pw, i, T, s_tiles, nt, S, N, U);
+        const i128 K = (i128)M * (i128)S - (i128)N * (i128)N;
+        const unsigned jc = sl[i].jc;
         if (K > bK || (K == bK && jc < bJ)) { bK = K; bJ = jc; }
     }
-    sp128(bK, s_khi[tid], s_klo[tid]);
-    s_j[tid] = bJ;
+    block_argmax(bK, bJ, s_hi, s_lo, s_j);
+    const i128 Kinc = bK;
+    const unsigned jinc = bJ;
     if (tid == 0) {
-        s_cnt = s.n_front;
-        s_overflow = 0;
+        sp128(Kinc, s.Kinc_hi, s.Kinc_lo);
+        s.j_inc = jinc;
+        s.point_evals += n_sel;
+        s.event_hyp += (long long)n_sel * p.n_events;
         s_pix = 0;
-        s_pruned = 0;
         s_nbound = 0;
-        s_quota_ctr = 0;
-        s_nsel_new = 0;
-        s_kids_new = 0;
-        s_stop = 0;
+        s_pruned = 0;
     }
-    for (int b = tid; b < 130; b += NT) s_hist[b] = 0;
+    for (int b = tid; b < 130; b += NTF) s_hist[b] = 0;
     __syncthreads();
-    if (tid == 0) {
-        i128 K0 = mk128(s_khi[0], s_klo[0]);
-        unsigned j0 = s_j[0];
-        for (int k = 1; k < NT; ++k) {
-            i128 K = mk128(s_khi[k], s_klo[k]);
-            if (K > K0 || (K == K0 && s_j[k] < j0)) { K0 = K; j0 = s_j[k]; }
-        }
-        sp128(K0, s.Kinc_hi, s.Kinc_lo);
-        s.j_inc = j0;
-        s.point_evals += s.n_sel;
-        s.event_hyp += (long long)s.n_sel * p.n_events;
-    }
-    __syncthreads();
-    const i128 Kinc = mk128(s.Kinc_hi, s.Kinc_lo);
-    const unsigned jinc = s.j_inc;
 
-    // (2) children of the expanded nodes: bound key, insert if improvable
-    for (int c = tid; c < 2 * s.n_sel; c += NT) {
-        const int i = c >> 1;
-        if (!sl[i].kids) continue;
-        unsigned long long S = 0, U = 0;
-        long long N = 0;
-        for (int t = 0; t < T; ++t) {
-            if (so[t + 1] > so[t]) {
-                const Part& q = pw[(long long)(F + c) * T + t];
-                S += q.S;
-                N += q.N;
-                U += q.U;
-            }
+    // (2) children of the expanded nodes, appended in slot order
+    int n = s.n_front;
+    int overflow = 0;
+    for (int c0 = 0; c0 < 2 * n_sel; c0 += NTF) {
+        const int c = c0 + tid;
+        int keep = 0;
+        Node nd;
+        if (c < 2 * n_sel && sl[c >> 1].kids) {
+            unsigned long long S, U;
+            long long N;
+            slot_sums(pw, F + c, T, s_tiles, nt, S, N, U);
+            atomicAdd(&s_pix, U);
+            atomicAdd((unsigned long long*)&s_nbound, 1ull);
+            const i128 Kb = (i128)M * (i128)S - (i128)N * (i128)N;
+            const Sel x = sl[c >> 1];
+            nd.ja = (c & 1) ? x.jc : x.ja;
+            nd.jb = (c & 1) ? x.jb : x.jc;
+            sp128(Kb, nd.khi, nd.klo);
+            keep = improvable(Kb, nd.ja, Kinc, jinc) ? 1 : 0;
+            if (!keep) atomicAdd((unsigned long long*)&s_pruned, 1ull);
         }
-        atomicAdd(&s_pix, U);
-        atomicAdd((unsigned long long*)&s_nbound, 1ull);
-        i128 Kb = (i128)M * (i128)S - (i128)N * (i128)N;
-        unsigned ja = (c & 1) ? sl[i].jc : sl[i].ja;
-        unsigned jb = (c & 1) ? sl[i].jb : sl[i].jc;
-        if (improvable(Kb, ja, Kinc, jinc)) {
-            int pos = atomicAdd(&s_cnt, 1);
-            if (pos < CAP) {
-                Node nd;
-                sp128(Kb, nd.khi, nd.klo);
-                nd.ja = ja;
-                nd.jb = jb;
-                fr[pos] = nd;
-            } else {
-                s_overflow = 1;
-            }
-        } else {
-            atomicAdd((unsigned long long*)&s_pruned, 1ull);
+        int tot;
+        const int r = block_scan(keep, s_wave, tot);
+        if (keep) {
+            if (n + r < CAP) fr[n + r] = nd;
         }
+        if (n + tot > CAP) overflow = 1;
+        n = min(n + tot, CAP);
     }
     __syncthreads();
+
+    // (3) which queued nodes can still improve; histogram of their gap sizes
+    i128 best_gap = -1;
+    for (int i = tid; i < n; i += NTF) {
+        const Node nd = fr[i];
+        const i128 k = mk128(nd.khi, nd.klo);
+        if (improvable(k, nd.ja, Kinc, jinc)) {
+            const i128 gap = k - Kinc;
+            atomicAdd(&s_hist[bitlen128(gap)], 1);
+            if (gap > best_gap) best_gap = gap;
+        }
+    }
+    unsigned jdummy = 0;
+    block_argmax(best_gap, jdummy, s_hi, s_lo, s_j);
     if (tid == 0) {
         s.bound_evals += s_nbound;
         s.event_hyp += s_nbound * p.n_events;
         s.pixel_updates += (long long)s_pix;
         s.nodes_pruned += s_pruned;
-    }
-    const int n = min(s_cnt, CAP);
-
-    // (3) which queued nodes can still improve; histogram of their gap sizes
-    long long my_gap_hi = -1;
-    unsigned long long my_gap_lo = 0;
-    i128 best_gap = -1;
-    for (int i = tid; i < n; i += NT) {
-        Node nd = fr[i];
-        i128 k = mk128(nd.khi, nd.klo);
-        if (improvable(k, nd.ja, Kinc, jinc)) {
-            i128 gap = k - Kinc;
-            atomicAdd(&s_hist[bitlen128(gap)], 1);
-            if (gap > best_gap) best_gap = gap;
-        }
-    }
-    sp128(best_gap, my_gap_hi, my_gap_lo);
-    s_khi[tid] = my_gap_hi;
-    s_klo[tid] = my_gap_lo;
-    __syncthreads();
-    if (tid == 0) {
-        i128 g = -1;
-        for (int k = 0; k < NT; ++k) {
-            i128 v = mk128(s_khi[k], s_klo[k]);
-            if (v > g) g = v;
-        }
         int n_keep = 0;
         for (int b = 0; b < 130; ++b) n_keep += s_hist[b];
         int stop = 0;
-        if (s_overflow) {
+        if (overflow) {
             s.status = -5;  // ECMD_EFRONTIER
             sp128((i128)-1, s.gap_hi, s.gap_lo);
             stop = 1;
@@ -745,25 +820,24 @@ __global__ __launch_bounds__(kFrontThreads) void k_frontier(
             s.gap_hi = 0;
             s.gap_lo = 0;
             stop = 1;
-        } else if (sp.gamma_key >= 0 && g <= (i128)sp.gamma_key) {
+        } else if (sp.gamma_key >= 0 && best_gap <= (i128)sp.gamma_key) {
             s.status = 0;
-            sp128(g, s.gap_hi, s.gap_lo);
+            sp128(best_gap, s.gap_hi, s.gap_lo);
             s.nodes_pruned += n_keep;
             stop = 1;
         }
         int take = min(F, n_keep);
         if (!stop && sp.max_nodes > 0) {
-            long long left = sp.max_nodes - s.nodes_expanded;
+            const long long left = sp.max_nodes - s.nodes_expanded;
             if (left <= 0) {
                 s.status = -4;  // ECMD_EBUDGET
-                sp128(g, s.gap_hi, s.gap_lo);
+                sp128(best_gap, s.gap_hi, s.gap_lo);
                 stop = 1;
             } else if (left < take) {
                 take = (int)left;
             }
         }
-        // threshold bucket: take every node of a larger gap class, and
-        // `quota` of the class b*
+        // take every node of a larger gap class and the first `quota` of class b*
         int cum = 0, bstar = 0, quota = 0;
         if (!stop) {
             for (int b = 129; b >= 0; --b) {
@@ -774,7 +848,7 @@ __global__ __launch_bounds__(kFrontThreads) void k_frontier(
         s_bstar = bstar;
         s_quota = quota;
         s_stop = stop;
-        s_out = 0;
+        s_take = take;
     }
     __syncthreads();
     if (s_stop) {
@@ -789,60 +863,57 @@ __global__ __launch_bounds__(kFrontThreads) void k_frontier(
     }
 
     // (4) split the queue into the nodes expanded now and the rest (in place)
-    for (int base = 0; base < n; base += NT) {
+    int out = 0, nsel = 0, inb = 0;
+    for (int base = 0; base < n; base += NTF) {
         const int i = base + tid;
         Node nd;
-        int keep = 0, take = 0;
+        int keep = 0, cand = 0, big = 0;
         if (i < n) {
             nd = fr[i];
-            i128 k = mk128(nd.khi, nd.klo);
+            const i128 k = mk128(nd.khi, nd.klo);
             if (improvable(k, nd.ja, Kinc, jinc)) {
-                int b = bitlen128(k - Kinc);
-                if (b > s_bstar) take = 1;
-                else if (b == s_bstar && atomicAdd(&s_quota_ctr, 1) < s_quota) take = 1;
-                else keep = 1;
+                const int b = bitlen128(k - Kinc);
+                big = b > s_bstar;
+                cand = b == s_bstar;
+                keep = !big && !cand;
             }
         }
-        s_scan[tid] = keep;
-        __syncthreads();
-        for (int o = 1; o < NT; o <<= 1) {
-            int a = tid >= o ? s_scan[tid - o] : 0;
-            __syncthreads();
-            s_scan[tid] += a;
-            __syncthreads();
-        }
-        const int out0 = s_out;
-        if (keep) fr[out0 + s_scan[tid] - 1] = nd;
+        int tot_c;
+        const int rc = block_scan(cand, s_wave, tot_c);
+        const int take = big || (cand && inb + rc < s_quota);
+        if (cand && !take) keep = 1;
+        inb += tot_c;
+        int tot_k, tot_t;
+        const int rk = block_scan(keep, s_wave, tot_k);
+        const int rt = block_scan(take, s_wave, tot_t);
+        if (keep) fr[out + rk] = nd;
         if (take) {
-            int k = atomicAdd(&s_nsel_new, 1);
             Sel x;
             x.ja = nd.ja;
             x.jb = nd.jb;
             x.jc = (nd.ja + nd.jb) >> 1;
             x.kids = (nd.jb - nd.ja >= 4) ? 1u : 0u;
-            sl[k] = x;
+            sl[nsel + rt] = x;
         }
-        __syncthreads();
-        if (tid == NT - 1) s_out = out0 + s_scan[NT - 1];
-        __syncthreads();
+        out += tot_k;
+        nsel += tot_t;
     }
+    __syncthreads();
     if (tid == 0) {
-        s.n_front = s_out;
-        s.n_sel = s_nsel_new;
-        s.nodes_expanded += s_nsel_new;
+        s.n_front = out;
+        s.n_sel = nsel;
+        s.nodes_expanded += nsel;
         s.steps += 1;
         st[w] = s;
     }
-    __syncthreads();
-    emit_hyps(sp, p, w, T, seg_off, sl, s_nsel_new, hyps + (long long)w * HS, items, qf);
+    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, items, qf, s_wave);
 }
 
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
                            const Part* part, Item* items, Queue* q_fill, int* n_active) {
     if (B <= 0) return hipSuccess;
-    k_frontier<<<B, kFrontThreads, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, part, items, q_fill,
-                                          n_active);
+    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, part, items, q_fill, n_active);
     return hipGetLastError();
 }
 

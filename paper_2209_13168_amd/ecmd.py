@@ -59,6 +59,11 @@ class ResultS(C.Structure):
                 ("steps", C.c_int32), ("seeded", C.c_int32)]
 
 
+class TuningS(C.Structure):
+    _fields_ = [("frontier_batch", C.c_int32), ("tile_px", C.c_int32), ("graph", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class ProfileS(C.Structure):
     _fields_ = [("calls", C.c_int64), ("eval_launches", C.c_int64), ("eval_ms", C.c_double),
                 ("frontier_launches", C.c_int64), ("frontier_ms", C.c_double), ("prep_ms", C.c_double)]
@@ -113,6 +118,10 @@ def _load():
                               vp, vp, vp], C.c_int),
         "ecmd_downsample": ([vp, C.POINTER(Sensor), vp, vp, vp, i32, u32, vp], C.c_int),
         "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
+        "ecmd_ctx_set_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
+        "ecmd_ctx_get_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
+        "ecmd_autotune": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32, C.POINTER(SearchS), u32,
+                           C.POINTER(TuningS), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_get_profile": ([vp, C.POINTER(ProfileS), C.c_int], C.c_int),
         "ecmd_cnn_create": ([vp, C.c_uint64, C.POINTER(vp)], C.c_int),
         "ecmd_cnn_destroy": ([vp], None),
@@ -232,6 +241,53 @@ class Context:
 
     def last_error(self) -> str:
         return lib().ecmd_last_error(self.h).decode()
+
+    def set_tuning(self, frontier_batch: int = 0, tile_px: int = 0, graph: bool = False):
+        t = TuningS(int(frontier_batch), int(tile_px), 1 if graph else 0, 0)
+        self._check(lib().ecmd_ctx_set_tuning(self.h, C.byref(t)))
+
+    def tuning(self) -> dict:
+        t = TuningS()
+        self._check(lib().ecmd_ctx_get_tuning(self.h, C.byref(t)))
+        return {"frontier_batch": t.frontier_batch, "tile_px": t.tile_px, "graph": bool(t.graph)}
+
+    def autotune(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float, eps: float,
+                 cache: Optional[str] = None) -> dict:
+        """Pick the fastest launch tuning for this kind of batch (kept in the
+        context).  With a cache file (JSON; default $ECMD_TUNE_CACHE) the
+        result is stored under a key of sensor size, batch size and mean
+        event count, and reused on later calls."""
+        import json
+
+        cache = cache or os.environ.get("ECMD_TUNE_CACHE")
+        B = int(tau.shape[0])
+        n_mean = int(offsets[-1] - offsets[0]) // max(B, 1)
+        key = f"{sensor.width}x{sensor.height}/B{1 << max(B - 1, 0).bit_length()}/N{1 << max(n_mean - 1, 0).bit_length()}"
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                known = json.load(f)
+            if key in known:
+                self.set_tuning(**{k: known[key][k] for k in ("frontier_batch", "tile_px", "graph")})
+                return dict(known[key], cached=True)
+        a = _Args()
+        px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        po, ptau = a.ptr(offsets, np.int64), a.ptr(tau, np.float32)
+        sp = _search(d_lo, d_hi, eps)
+        best = TuningS()
+        ms = C.c_double()
+        self._check(lib().ecmd_autotune(self.h, C.byref(sensor), px, py, pt, po, ptau, B, C.byref(sp), a.flags,
+                                        C.byref(best), C.byref(ms)))
+        out = {"frontier_batch": best.frontier_batch, "tile_px": best.tile_px, "graph": bool(best.graph),
+               "ms": ms.value}
+        if cache:
+            known = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    known = json.load(f)
+            known[key] = out
+            with open(cache, "w") as f:
+                json.dump(known, f, indent=1, sort_keys=True)
+        return dict(out, cached=False)
 
     def set_profiling(self, enable: bool = True):
         self._check(lib().ecmd_ctx_set_profiling(self.h, 1 if enable else 0))

@@ -1,0 +1,87 @@
+"""Full-size batches in the benchmark's launch configuration: the 64-window
+640x480 batch (50k-1M events per window) and the 256-window 1280x720 batch
+(0.1-5M events per window plus hot pixels).  Windows whose oracle optimum
+was computed ahead of time (tests/golden/oracle_optima.json, written by
+tests/golden/make_golden.py from the oracle alone) must match exactly; for
+the others the returned key must equal the oracle's key at the returned
+grid point and be at least the oracle's key at the true divergence's grid
+point (properties that hold at any size)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_optima.json")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2209_13168_amd import ecmd
+
+    c = ecmd.Context(0)
+    yield c
+    c.close()
+
+
+def _golden(cfg):
+    rows = json.load(open(GOLDEN))["windows"]
+    return {r["window"]: r for r in rows if r["config"] == cfg}
+
+
+def _run(ctx, cfg, B):
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+    from paper_2209_13168_amd.learned import windows_chunks
+    from synth.ventral import config_specs
+
+    xs, ys, ts, taus, ns = [], [], [], [], []
+    for x, y, t, offs, tau, _ in windows_chunks(list(range(B)), cfg=cfg, chunk=16):
+        xs.append(x)
+        ys.append(y)
+        ts.append(t)
+        taus.append(tau)
+        ns += list(np.diff(offs))
+    off = np.zeros(B + 1, np.int64)
+    off[1:] = np.cumsum(ns)
+    dev = torch.device("cuda:0")
+    args = [torch.from_numpy(np.concatenate(a)).to(dev) for a in (xs, ys, ts)]
+    s = config_specs(cfg, 0)
+    print(f"{cfg}: {B} windows, {int(off[-1])} events", flush=True)
+    res = ctx.estimate_batched(ecmd.sensor(s.width, s.height, s.foe), *args, torch.from_numpy(off).to(dev),
+                               torch.from_numpy(np.concatenate(taus)).to(dev), s.d_lo, s.d_hi, s.eps)
+    return res, s, off
+
+
+def _check(ctx, orc, cfg, B, n_sampled):
+    from synth import config_windows
+
+    res, s, off = _run(ctx, cfg, B)
+    assert all(r.status == 0 for r in res)
+    gold = _golden(cfg)
+    for k, g in gold.items():
+        assert res[k].n_events == g["n_events"]
+        assert (res[k].j_star, res[k].K) == (g["j_star"], int(g["K"])), (cfg, k)
+    sizes = np.diff(off)
+    others = [int(k) for k in np.argsort(sizes) if int(k) not in gold][:n_sampled]
+    L = res[0].L
+    for k in others:
+        w = config_windows(cfg, [k])[0]
+        ev = orc.Events.of_window(w)
+        S, N = orc.point(ev, orc.grid_d(s.d_lo, s.d_hi, L, res[k].j_star))
+        assert orc.key(ev.M, S, N) == res[k].K, (cfg, k)
+        jt = int(round((w.spec.d_true - s.d_lo) / (s.d_hi - s.d_lo) * (1 << L)))
+        S, N = orc.point(ev, orc.grid_d(s.d_lo, s.d_hi, L, jt))
+        assert res[k].K >= orc.key(ev.M, S, N), (cfg, k)
+
+
+def test_full_640x480_batch(ctx, orc):
+    _check(ctx, orc, "c3", 64, 4)
+
+
+def test_full_1280x720_batch_with_hot_pixels(ctx, orc):
+    _check(ctx, orc, "c5", 256, 3)

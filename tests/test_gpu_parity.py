@@ -252,3 +252,41 @@ def test_downsample_bit_exact(ctx, orc):
     got = ctx.downsample(_sensor(s), x, y, off).reshape(len(ws), 64, 64)
     for i, w in enumerate(ws):
         assert np.array_equal(got[i], orc.downsample(w.x, w.y, s.width, s.height))
+
+
+def test_graph_replay_and_tunings_match(ctx, orc):
+    """The captured step graph, replayed across several calls with eager
+    calls in between, and every tuning the autotuner may pick, give the
+    oracle's optima."""
+    ws = config_windows("c2", range(5), n_events=12_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    sen = _sensor(s)
+    want = [orc.bnb(orc.Events.of_window(w), s.d_lo, s.d_hi, 1e-4) for w in ws]
+    saved = ctx.tuning()
+    try:
+        for F, tile, graph in [(64, 0, True), (16, 0, True), (64, 11000, False), (128, 6000, True),
+                               (64, 0, False), (64, 0, True)]:
+            ctx.set_tuning(F, tile, graph)
+            for _ in range(2):
+                got = ctx.estimate_batched(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+                for r, o in zip(got, want):
+                    _check_same(r, o)
+        best = ctx.autotune(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+        assert best["frontier_batch"] in (16, 32, 64, 128, 256)
+        got = ctx.estimate_batched(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+        for r, o in zip(got, want):
+            _check_same(r, o)
+    finally:
+        ctx.set_tuning(**saved)
+
+
+def test_search_is_reproducible(ctx):
+    """Node counts, steps and pixel counts are identical call after call (the
+    frontier step orders everything by scans, not by atomic races)."""
+    ws = config_windows("c2", range(3), n_events=20_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    runs = [ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4) for _ in range(3)]
+    key = lambda rs: [(r.j_star, r.K, r.nodes_expanded, r.bound_evals, r.pixel_updates, r.steps) for r in rs]
+    assert key(runs[0]) == key(runs[1]) == key(runs[2])
