@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--plain-windows", type=int, default=8, help="windows timed one call each")
     ap.add_argument("--cpu-windows", type=int, default=3, help="oracle sample size (windows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
+                    help="trained proposal network (the step seeds the search with it when present)")
+    ap.add_argument("--plain", action="store_true", help="time the search without the learned seeds")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB buffer three times (to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -66,6 +71,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 3}))
+        return
     B = args.windows
     wins = config_windows("c2", range(B))
     s = wins[0].spec
@@ -74,9 +87,19 @@ def main():
     sensor = ecmd.sensor(s.width, s.height, s.foe)
     ctx = ecmd.Context(0)
     kw = dict(frontier_batch=args.frontier_batch)
+    net = None
+    if not args.plain and os.path.exists(args.weights):
+        from paper_2209_13168_amd import learned
 
-    def step():
+        net, net_meta = learned.load(ctx, args.weights)
+
+    def step_plain():
         return ctx.estimate_batched(sensor, dx, dy, dt, doff, dtau, s.d_lo, s.d_hi, s.eps, **kw)
+
+    def step_learned():
+        return ctx.estimate_learned(net, sensor, dx, dy, dt, doff, dtau, s.d_lo, s.d_hi, s.eps, **kw)
+
+    step = step_learned if net is not None else step_plain
 
     ref = None
     for _ in range(args.warmup):
@@ -103,6 +126,20 @@ def main():
     bd_ev = sum(r.bound_evals * r.n_events for r in last)
     pix = sum(r.pixel_updates for r in last)
     value = ev_hyp / sec
+
+    # batched without the learned seeds (same timing method, fewer steps)
+    batched_plain_ws = None
+    if net is not None:
+        step_plain()
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        reps = max(3, args.steps // 4)
+        for _ in range(reps):
+            rp = step_plain()
+        torch.cuda.synchronize()
+        batched_plain_ws = B * reps / (time.perf_counter() - a0)
+        assert [(r.j_star, r.K) for r in rp] == [(r.j_star, r.K) for r in last]
+        nodes_plain = float(np.mean([r.nodes_expanded for r in rp]))
 
     # plain: one window per call, no batching
     P = min(args.plain_windows, B)
@@ -154,18 +191,22 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{B} windows of the 346x260 config per step: 100k events/0.25 s window, "
-                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB",
+                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB"
+                        + (" seeded by the learned proposal" if net is not None else ""),
             "windows_per_step": B,
             "events_per_window": int(n_w.mean()),
             "eps": s.eps,
             "frontier_batch": args.frontier_batch or 64,
         },
         "windows_per_s": {
-            "batched": round(B / sec, 2),
-            "plain_one_window_per_call": round(P / sum(plain_t), 2),
+            ("batched_learned" if net is not None else "batched"): round(B / sec, 2),
+            "batched": round(batched_plain_ws, 2) if batched_plain_ws else round(B / sec, 2),
+            "plain_one_window_per_call": round(P / sum(plain_t), 2) if plain_t else None,
         },
         "search": {
             "nodes_expanded_mean": float(np.mean([r.nodes_expanded for r in last])),
+            "nodes_expanded_mean_without_seeds": nodes_plain if net is not None else None,
+            "learned_seeds": net is not None,
             "steps_max": int(max(r.steps for r in last)),
             "point_event_evals": int(pt_ev),
             "interval_event_evals": int(bd_ev),

@@ -384,15 +384,16 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     HIPCHK(c, c->front.ensure(sizeof(Node) * (size_t)B * sp.CAP));
     HIPCHK(c, c->sel.ensure(sizeof(Sel) * (size_t)B * sp.F));
     HIPCHK(c, c->hyps.ensure(sizeof(Hyp) * (size_t)B * sp.HS));
-    HIPCHK(c, c->items.ensure(sizeof(Item) * (size_t)B * sp.HS * T));
-    HIPCHK(c, c->queues.ensure(sizeof(Queue) * 2));
+    const int qcap = ((B + kXcd - 1) / kXcd) * sp.HS * T;  // windows w = r (mod kXcd) share queue r
+    HIPCHK(c, c->items.ensure(sizeof(Item) * (size_t)kXcd * qcap));
+    HIPCHK(c, c->queues.ensure(sizeof(Queue) * 2 * kXcd));
     HIPCHK(c, c->part.ensure(sizeof(Part) * (size_t)B * sp.HS * T));
     HIPCHK(c, c->n_active.ensure(sizeof(int)));
-    HIPCHK(c, hipMemsetAsync(c->queues.p, 0, sizeof(Queue) * 2, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->queues.p, 0, sizeof(Queue) * 2 * kXcd, c->stream));
     HIPCHK(c, hipMemsetAsync(c->n_active.p, 0, sizeof(int), c->stream));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
-                          c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[0], T,
+                          c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->items.as<Item>(), qcap, &q[0], T,
                           c->seg_off.as<long long>()));
     const size_t lds = eval_lds_bytes(g.max_tile_px);
     HIPCHK(c, eval_set_lds(lds));
@@ -404,14 +405,16 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         for (int parity = 0; parity < 2; ++parity) {
             if (timed) tm.begin();
             hipError_t e = launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[parity],
-                                       &q[1 - parity], c->part.as<Part>(), sp.HS, nullptr);
+                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), qcap,
+                                       &q[parity * kXcd], &q[(1 - parity) * kXcd], c->part.as<Part>(), sp.HS,
+                                       nullptr);
             if (e != hipSuccess) return e;
             if (timed) tm.end(0);
             if (timed) tm.begin();
             e = launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
                                 c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(), c->hyps.as<Hyp>(),
-                                c->part.as<Part>(), c->items.as<Item>(), &q[1 - parity], c->n_active.as<int>());
+                                c->part.as<Part>(), c->items.as<Item>(), qcap, &q[(1 - parity) * kXcd],
+                                c->n_active.as<int>());
             if (e != hipSuccess) return e;
             if (timed) tm.end(1);
         }
@@ -430,7 +433,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         put(ptrs, sizeof ptrs);
         put(&g, sizeof g);
         put(&sp, sizeof sp);
-        int ints[] = {B, T, nb, (int)lds};
+        int ints[] = {B, T, nb, (int)lds, qcap};
         put(ints, sizeof ints);
         if (!c->gexec || key != c->gkey) {
             if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -859,7 +862,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     HIPCHK(c, c->items.ensure(sizeof(Item) * items.size()));
     HIPCHK(c, hipMemcpyAsync(c->items.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
                              c->stream));
-    Queue hq[2] = {{(int)items.size(), 0}, {0, 0}};
+    Queue hq[2 * kXcd] = {};
+    hq[0].n_items = (int)items.size();  // everything in queue 0; the other XCDs steal
     HIPCHK(c, c->queues.ensure(sizeof hq));
     HIPCHK(c, hipMemcpyAsync(c->queues.p, hq, sizeof hq, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, c->part.ensure(sizeof(Part) * items.size()));
@@ -876,8 +880,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     HIPCHK(c, eval_set_lds(lds));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_eval(c->stream, g, eval_blocks(c, lds), lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), &q[0], &q[1],
-                          c->part.as<Part>(), m, dimg));
+                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), (int)items.size(), &q[0],
+                          &q[kXcd], c->part.as<Part>(), m, dimg));
     std::vector<Part> parts(items.size());
     std::vector<long long> seg(T + 1);
     HIPCHK(c, hipMemcpyAsync(parts.data(), c->part.p, sizeof(Part) * parts.size(), hipMemcpyDeviceToHost,

@@ -101,6 +101,12 @@ struct Item {
     int t;   // tile
 };
 
+// Work queues: one per XCD (workgroups are dispatched to the 8 XCDs in
+// round-robin order of their index), so that the items of a window are
+// evaluated on one XCD and its events stay in that XCD's L2.  Queue r owns
+// the item slots [r * qcap, (r + 1) * qcap).
+constexpr int kXcd = 8;
+
 struct Queue {
     int n_items;
     int next;
@@ -120,14 +126,15 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
                        unsigned long long* cursor, float4* ev, int* err_flag);
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
-                       WinState* st, Sel* sel, Hyp* hyps, Item* items, Queue* q, int T,
+                       WinState* st, Sel* sel, Hyp* hyps, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off);
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
-                           const Part* part, Item* items, Queue* q_fill, int* n_active);
+                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active);
+// q, q_reset: kXcd queues each
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes,
                        const float4* ev, const long long* seg_off, const int* seg_own,
-                       const Hyp* hyps, const Item* items, Queue* q, Queue* q_reset, Part* part,
+                       const Hyp* hyps, const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part,
                        int HS, unsigned* img_out);
 hipError_t launch_rates(hipStream_t s, const float* d_a, const float* d_b, int m, float tau, Hyp* hyps);
 hipError_t launch_probe_pixels(hipStream_t s, const float* x, const float* y, const float* t_rel,

@@ -353,7 +353,7 @@ size_t eval_lds_bytes(int max_tile_px) {
 // so the sum of squares is sum(2*old + 1) with no pass over the tile.
 __global__ __launch_bounds__(kEvalThreads) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
-    const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const Item* __restrict__ items,
+    const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const Item* __restrict__ items, int qcap,
     Queue* __restrict__ q, Queue* __restrict__ q_reset, Part* __restrict__ part, int HS,
     unsigned* __restrict__ img_out) {
     extern __shared__ unsigned smem[];
@@ -362,18 +362,31 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     unsigned long long* const s_red =
         reinterpret_cast<unsigned long long*>(smem + g.max_tile_px + kEvalThreads);
     int* const s_item = reinterpret_cast<int*>(s_red + 3 * kEvalWaves);
-    if (blockIdx.x == 0 && tid == 0 && q_reset) {
-        q_reset->n_items = 0;
-        q_reset->next = 0;
+    if (blockIdx.x == 0 && tid < kXcd && q_reset) {
+        q_reset[tid].n_items = 0;
+        q_reset[tid].next = 0;
     }
-    const int n_items = q->n_items;
     const float Wf = (float)g.W, Hf = (float)g.H;
+    const int home = blockIdx.x % kXcd;
+    int qi = 0;  // queues tried so far, starting at this XCD's own (thread 0 only)
     for (;;) {
-        if (tid == 0) *s_item = atomicAdd(&q->next, 1);
+        if (tid == 0) {
+            int got = -1;
+            while (qi < kXcd) {
+                const int r = (home + qi) % kXcd;
+                const int k = atomicAdd(&q[r].next, 1);
+                if (k < q[r].n_items) {
+                    got = r * qcap + k;
+                    break;
+                }
+                ++qi;
+            }
+            *s_item = got;
+        }
         __syncthreads();
         const int it = *s_item;
         __syncthreads();
-        if (it >= n_items) break;
+        if (it < 0) break;
         const Item item = items[it];
         const int w = item.wh / HS, t = item.t;
         const Hyp hp = hyps[item.wh];
@@ -513,8 +526,8 @@ hipError_t eval_set_lds(size_t bytes) {
 
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes, const float4* ev,
                        const long long* seg_off, const int* seg_own, const Hyp* hyps, const Item* items,
-                       Queue* q, Queue* q_reset, Part* part, int HS, unsigned* img_out) {
-    k_eval<<<nblocks, kEvalThreads, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, items, q, q_reset, part,
+                       int qcap, Queue* q, Queue* q_reset, Part* part, int HS, unsigned* img_out) {
+    k_eval<<<nblocks, kEvalThreads, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, items, qcap, q, q_reset, part,
                                                    HS, img_out);
     return hipGetLastError();
 }
@@ -586,7 +599,9 @@ __device__ __forceinline__ void slot_sums(const Part* pw, int slot, int T, const
 
 // Hypotheses of the selected nodes and their work items.
 __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
-                          const Sel* sl, int n_sel, Hyp* hy, Item* items, Queue* qf, int* s_wave) {
+                          const Sel* sl, int n_sel, Hyp* hy, Item* items, int qcap, Queue* qf, int* s_wave) {
+    const int qr = w % kXcd;  // this window's queue
+    Item* qitems = items + (long long)qr * qcap;
     const int F = sp.F, HS = sp.HS;
     __shared__ int s_base;
     // slots with work: points [0, n_sel), intervals F + [0, 2 n_sel) of nodes with children
@@ -614,14 +629,14 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
         if (h < HS) hy[h] = hp;
         int tot;
         const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
-        if (threadIdx.x == 0) s_base = (tot * nt) ? atomicAdd(&qf->n_items, tot * nt) : 0;
+        if (threadIdx.x == 0) s_base = (tot * nt) ? atomicAdd(&qf[qr].n_items, tot * nt) : 0;
         __syncthreads();
         if (hp.kind != HYP_NONE)
-            for (int k = 0; k < nt; ++k) {
+            for (int k = 0; k < nt; ++k) {  // tile-major: items sharing events are adjacent
                 Item it;
                 it.wh = w * HS + h;
                 it.t = tiles[k];
-                items[s_base + r * nt + k] = it;
+                qitems[s_base + k * tot + r] = it;
             }
         __syncthreads();
     }
@@ -645,7 +660,7 @@ __device__ __forceinline__ void nonempty_tiles(int w, int T, const long long* se
 __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restrict__ wp,
                                               const float* __restrict__ seeds, int B, WinState* __restrict__ st,
                                               Sel* __restrict__ sel, Hyp* __restrict__ hyps,
-                                              Item* __restrict__ items, Queue* __restrict__ q, int T,
+                                              Item* __restrict__ items, int qcap, Queue* __restrict__ q, int T,
                                               const long long* __restrict__ seg_off) {
     const int w = blockIdx.x;
     const unsigned top = 1u << sp.L;
@@ -689,14 +704,14 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
     }
     __syncthreads();
     nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
-    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, items, q, s_wave);
+    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, items, qcap, q, s_wave);
 }
 
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
-                       WinState* st, Sel* sel, Hyp* hyps, Item* items, Queue* q, int T,
+                       WinState* st, Sel* sel, Hyp* hyps, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off) {
     if (B <= 0) return hipSuccess;
-    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, items, q, T, seg_off);
+    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, items, qcap, q, T, seg_off);
     return hipGetLastError();
 }
 
@@ -708,7 +723,7 @@ hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, cons
 __global__ __launch_bounds__(NTF) void k_frontier(
     Search sp, const WinParam* __restrict__ wp, int B, int T, const long long* __restrict__ seg_off,
     WinState* __restrict__ st, Node* __restrict__ front, Sel* __restrict__ sel, Hyp* __restrict__ hyps,
-    const Part* __restrict__ part, Item* __restrict__ items, Queue* __restrict__ qf,
+    const Part* __restrict__ part, Item* __restrict__ items, int qcap, Queue* __restrict__ qf,
     int* __restrict__ n_active) {
     const int w = blockIdx.x, tid = threadIdx.x;
     __shared__ WinState s;
@@ -906,14 +921,15 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s.steps += 1;
         st[w] = s;
     }
-    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, items, qf, s_wave);
+    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, items, qcap, qf, s_wave);
 }
 
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
-                           const Part* part, Item* items, Queue* q_fill, int* n_active) {
+                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active) {
     if (B <= 0) return hipSuccess;
-    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, part, items, q_fill, n_active);
+    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, part, items, qcap, q_fill,
+                                n_active);
     return hipGetLastError();
 }
 
