@@ -221,6 +221,31 @@ int ecmd_probe_bound(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
                      int32_t m, uint32_t flags, uint64_t *S_bar, int64_t *N_low,
                      uint32_t *img_out);
 
+/* --------------------------------------------------------- preprocessing */
+
+/* Both calls copy the kept events of every window, in order, to x_out,
+ * y_out, t_out (capacity offsets[B] - offsets[0] each) and write the new
+ * window offsets to offsets_out (B + 1 values, starting at 0).  Windows and
+ * pointers as in ecmd_estimate_divergence_batched. */
+
+/* Hot-pixel removal (Sec. 6, "Preprocessing"): drop every event of a pixel
+ * (floor(x), floor(y)) that holds more than max_count events of its window. */
+int ecmd_hot_pixel_filter(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
+                          const float *y, const float *t_rel, const int64_t *offsets,
+                          int32_t B, int32_t max_count, uint32_t flags, float *x_out,
+                          float *y_out, float *t_out, int64_t *offsets_out);
+
+/* "Resized and resampled" data (Sec. 6): coordinates scaled to the output
+ * sensor, x' = x * float(W_out / W_in), y' = y * float(H_out / H_in) (fp32),
+ * and event k of window w (k from the window start) kept iff
+ * (SplitMix64(seed + (w * 2^32 + k + 1) * 0x9E3779B97F4A7C15) >> 40) <
+ * floor(keep_frac * 2^24), i.e. with probability keep_frac (the paper keeps
+ * 25%).  The output sensor's FOE is the caller's (normally the scaled one). */
+int ecmd_resample(ecmd_ctx *ctx, const ecmd_sensor *in_sensor, const ecmd_sensor *out_sensor,
+                  const float *x, const float *y, const float *t_rel, const int64_t *offsets,
+                  int32_t B, float keep_frac, uint64_t seed, uint32_t flags, float *x_out,
+                  float *y_out, float *t_out, int64_t *offsets_out);
+
 /* ------------------------------------------------ learned incumbent */
 
 typedef struct ecmd_cnn ecmd_cnn;

@@ -1003,6 +1003,120 @@ int ecmd_downsample(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, cons
 
 }  // extern "C"
 
+// ------------------------------------------------------------ preprocessing
+
+// kind 0: hot-pixel removal (max_count); kind 1: resize + resample
+static int preproc_impl(ecmd_ctx* c, int kind, const ecmd_sensor* in_s, const ecmd_sensor* out_s, const float* x,
+                        const float* y, const float* t_rel, const int64_t* offsets, int32_t B, int32_t max_count,
+                        float keep_frac, uint64_t seed, uint32_t flags, float* x_out, float* y_out, float* t_out,
+                        int64_t* offsets_out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    int rc = check_sensor(c, in_s);
+    if (rc) return rc;
+    if (kind == 1 && (rc = check_sensor(c, out_s))) return rc;
+    if (B < 0 || !offsets || !offsets_out) return fail(c, ECMD_EINVAL, "bad window arguments");
+    if (kind == 0 && max_count < 0) return fail(c, ECMD_EINVAL, "max_count must be >= 0");
+    if (kind == 1 && !(keep_frac >= 0.0f && keep_frac <= 1.0f)) return fail(c, ECMD_EINVAL, "keep_frac in [0, 1]");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<long long> off(B + 1);
+    if (flags & ECMD_DEVICE_PTR) {
+        HIPCHK(c, hipMemcpy(off.data(), offsets, sizeof(long long) * (B + 1), hipMemcpyDeviceToHost));
+    } else {
+        memcpy(off.data(), offsets, sizeof(long long) * (B + 1));
+    }
+    if (off[0] < 0) return fail(c, ECMD_EINVAL, "offsets[0] < 0");
+    for (int w = 0; w < B; ++w)
+        if (off[w + 1] < off[w]) return fail(c, ECMD_EINVAL, "offsets decrease at window %d", w);
+    const long long n = off[B] - off[0];
+    if (n > 0 && (!x || !y || !t_rel || !x_out || !y_out || !t_out)) return fail(c, ECMD_EINVAL, "NULL arrays");
+    // inputs: device pointers as given, host arrays staged (indexed from offsets[0])
+    const float *dx = x, *dy = y, *dt = t_rel;
+    const long long* doff = (const long long*)offsets;
+    long long base = off[0];
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->sx.ensure(sizeof(float) * std::max(n, 1ll)));
+        HIPCHK(c, c->sy.ensure(sizeof(float) * std::max(n, 1ll)));
+        HIPCHK(c, c->st.ensure(sizeof(float) * std::max(n, 1ll)));
+        if (n) {
+            HIPCHK(c, hipMemcpyAsync(c->sx.p, x + base, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->sy.p, y + base, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->st.p, t_rel + base, sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+        }
+        // staged copies start at index 0: shift the offsets
+        std::vector<long long> o0(off);
+        for (auto& v : o0) v -= base;
+        HIPCHK(c, c->soff.ensure(sizeof(long long) * (B + 1)));
+        HIPCHK(c, hipMemcpyAsync(c->soff.p, o0.data(), sizeof(long long) * (B + 1), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        dx = c->sx.as<float>();
+        dy = c->sy.as<float>();
+        dt = c->st.as<float>();
+        doff = c->soff.as<long long>();
+        base = 0;
+    }
+    HIPCHK(c, c->keep.ensure(std::max(n, 1ll)));
+    const long long nb = (n + 1023) / 1024;
+    HIPCHK(c, c->misc.ensure(sizeof(long long) * (nb + 1)));
+    unsigned char* keep = (unsigned char*)c->keep.p;
+    const int W = in_s->width, H = in_s->height;
+    if (kind == 0) {
+        const size_t M = (size_t)W * H;
+        HIPCHK(c, c->counts.ensure(sizeof(unsigned) * M * std::max(B, 1)));
+        HIPCHK(c, hipMemsetAsync(c->counts.p, 0, sizeof(unsigned) * M * std::max(B, 1), c->stream));
+        HIPCHK(c, launch_hot_keep(c->stream, dx, dy, doff, B, n, W, H, c->counts.as<unsigned>(), (unsigned)max_count,
+                                  keep));
+    } else {
+        const double th = floor((double)keep_frac * 16777216.0);
+        HIPCHK(c, launch_resample_keep(c->stream, doff, B, n, seed, (unsigned)th, keep));
+    }
+    const float sx = kind == 1 ? (float)out_s->width / (float)W : 1.0f;
+    const float sy = kind == 1 ? (float)out_s->height / (float)H : 1.0f;
+    float *ox = x_out, *oy = y_out, *ot = t_out;
+    long long* ooff = (long long*)offsets_out;
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->pix.ensure(sizeof(float) * 3 * std::max(n, 1ll) + sizeof(long long) * (B + 1)));
+        ox = c->pix.as<float>();
+        oy = ox + std::max(n, 1ll);
+        ot = oy + std::max(n, 1ll);
+        ooff = (long long*)(ot + std::max(n, 1ll));
+    }
+    HIPCHK(c, launch_compact(c->stream, dx, dy, dt, doff, B, base, n, keep, c->misc.as<long long>(), sx, sy, ox, oy,
+                             ot, ooff));
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        std::vector<long long> ho(B + 1);
+        HIPCHK(c, hipMemcpyAsync(ho.data(), ooff, sizeof(long long) * (B + 1), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const long long m = ho[B];
+        if (m) {
+            HIPCHK(c, hipMemcpyAsync(x_out, ox, sizeof(float) * m, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(y_out, oy, sizeof(float) * m, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(t_out, ot, sizeof(float) * m, hipMemcpyDeviceToHost, c->stream));
+        }
+        memcpy(offsets_out, ho.data(), sizeof(long long) * (B + 1));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return ECMD_OK;
+}
+
+extern "C" {
+
+int ecmd_hot_pixel_filter(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
+                          const int64_t* offsets, int32_t B, int32_t max_count, uint32_t flags, float* x_out,
+                          float* y_out, float* t_out, int64_t* offsets_out) {
+    return preproc_impl(c, 0, sensor, nullptr, x, y, t_rel, offsets, B, max_count, 1.0f, 0, flags, x_out, y_out,
+                        t_out, offsets_out);
+}
+
+int ecmd_resample(ecmd_ctx* c, const ecmd_sensor* in_sensor, const ecmd_sensor* out_sensor, const float* x,
+                  const float* y, const float* t_rel, const int64_t* offsets, int32_t B, float keep_frac,
+                  uint64_t seed, uint32_t flags, float* x_out, float* y_out, float* t_out, int64_t* offsets_out) {
+    return preproc_impl(c, 1, in_sensor, out_sensor, x, y, t_rel, offsets, B, 0, keep_frac, seed, flags, x_out, y_out,
+                        t_out, offsets_out);
+}
+
+}  // extern "C"
+
 // ------------------------------------------------------------ learned incumbent
 
 // Deterministic parameter initialisation: He-normal weights from a

@@ -152,6 +152,15 @@ hipError_t launch_select(hipStream_t s, const float* x, const float* y, const do
                          double t0, double t1, float* xo, float* yo, float* to, int* blk_cnt,
                          long long* total);
 
+// preprocessing (ecmd_preproc.hip)
+hipError_t launch_compact(hipStream_t s, const float* x, const float* y, const float* t, const long long* offsets,
+                          int B, long long off0, long long n, const unsigned char* keep, long long* blk, float sx,
+                          float sy, float* xo, float* yo, float* to, long long* off_out);
+hipError_t launch_resample_keep(hipStream_t s, const long long* offsets, int B, long long n, unsigned long long seed,
+                                unsigned thresh24, unsigned char* keep);
+hipError_t launch_hot_keep(hipStream_t s, const float* x, const float* y, const long long* offsets, int B, long long n,
+                           int W, int H, unsigned* counts, unsigned max_count, unsigned char* keep);
+
 // learned incumbent (ecmd_cnn.hip)
 size_t cnn_lds_bytes();
 int cnn_nparam();

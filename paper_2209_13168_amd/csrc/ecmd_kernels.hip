@@ -302,20 +302,29 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // counted by the caller.  Corner decisions follow the event's ray through
 // (x, y) with direction (ax, ay), in fp64: e = |X - x||ay| - |Y - y||ax|
 // compares where the ray meets the next vertical and horizontal pixel
-// edges; within 2^-8 px of the corner both side pixels are counted.  The
-// increments do not return values (the sum of squares comes from one pass
-// over the tile afterwards); pixels outside the tile go to the thread's
-// private spill word `spill`.
+// edges; within 2^-8 px of the corner both side pixels are counted.
+// Each increment returns the previous count; it is added to `sumold` one
+// increment later (`pend`), so the wait for it overlaps the next step.
+// Pixels outside the tile go to the thread's private spill word `spill`.
+struct WalkAcc {
+    unsigned long long sumold;
+    unsigned pend;
+    unsigned visits;
+};
+
 __device__ __forceinline__ void tile_add(unsigned* __restrict__ tile, unsigned spill, int x0, int y0, unsigned tw,
-                                         unsigned th, int px, int py) {
+                                         unsigned th, int px, int py, WalkAcc& acc) {
     const unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
     const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
-    __hip_atomic_fetch_add(&tile[a], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const unsigned old = atomicAdd(&tile[a], 1u);
+    acc.sumold += acc.pend;
+    acc.pend = old;
+    acc.visits += 1;
 }
 
 __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned spill, int x0, int y0,
                                           unsigned tw, unsigned th, int kx, int ky, int kxb, int kyb,
-                                          float xf, float yf, float axf, float ayf) {
+                                          float xf, float yf, float axf, float ayf, WalkAcc& acc) {
     const int sx = (kxb > kx) - (kxb < kx);
     const int sy = (kyb > ky) - (kyb < ky);
     const double x = (double)xf, y = (double)yf;
@@ -329,12 +338,12 @@ __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned 
         const double e = ex - ey;
         const bool lo = e < -thr, hi = e > thr;
         if (dx && dy && !lo && !hi) {  // the ray passes near the corner: both side pixels
-            tile_add(tile, spill, x0, y0, tw, th, kx + sx, ky);
-            tile_add(tile, spill, x0, y0, tw, th, kx, ky + sy);
+            tile_add(tile, spill, x0, y0, tw, th, kx + sx, ky, acc);
+            tile_add(tile, spill, x0, y0, tw, th, kx, ky + sy, acc);
         }
         kx += (dx && (!dy || !hi)) ? sx : 0;
         ky += (dy && (!dx || !lo)) ? sy : 0;
-        tile_add(tile, spill, x0, y0, tw, th, kx, ky);
+        tile_add(tile, spill, x0, y0, tw, th, kx, ky, acc);
     } while (kx != kxb || ky != kyb);
 }
 
@@ -402,7 +411,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         for (int i = tid; i < npx + kEvalThreads; i += kEvalThreads) tile[i] = 0u;
         __syncthreads();
 
-        unsigned long long sumold = 0, nlow = 0, nlow_sq = 0, nlow_cnt = 0;
+        unsigned long long sumold = 0, nlow = 0;
         unsigned visits = 0;
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
@@ -440,6 +449,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         } else {
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
+            WalkAcc acc{0ull, 0u, 0u};
             long long i = beg + tid;
             float4 e = i < end ? ev[i] : make_float4(0.f, 0.f, 0.f, 0.f);
             for (; i < end; i += kEvalThreads) {
@@ -450,37 +460,20 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 if (i < own_end && inside(xa, ya, Wf, Hf) && inside(xb, yb, Wf, Hf)) nlow += 1;
                 const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
-                tile_add(tile, spill, x0, y0, tw, th, kxa, kya);
+                tile_add(tile, spill, x0, y0, tw, th, kxa, kya, acc);
                 if (kxa != kxb || kya != kyb)
-                    walk_tile(tile, spill, x0, y0, tw, th, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
+                    walk_tile(tile, spill, x0, y0, tw, th, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
                 e = en;
             }
-            // S_bar and the increment count from one pass over the tile
-            __syncthreads();
-            unsigned long long sq = 0, cnt = 0;
-            for (int k = tid; k < npx; k += kEvalThreads) {
-                const unsigned long long h = tile[k];
-                sq += h * h;
-                cnt += h;
-            }
-            sumold = 0;
-            visits = 0;
-            nlow_sq = sq;
-            nlow_cnt = cnt;
+            sumold = acc.sumold + acc.pend;
+            visits = acc.visits;
         }
-        // Point items: remove the spill word, whose m increments returned
-        // 0, 1, .., m-1; then S = sum(2*old + 1) over the in-tile events.
-        // Interval items: S_bar = sum H_bar^2 and the count from the pass.
-        unsigned long long sq, hits;
-        if (hp.kind == HYP_POINT) {
-            const unsigned m = tile[spill];
-            sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
-            hits = (unsigned long long)(visits - m);
-            sq = 2ull * sumold + hits;
-        } else {
-            sq = nlow_sq;
-            hits = nlow_cnt;
-        }
+        // Remove the spill word, whose m increments returned 0, 1, .., m-1;
+        // then the sum of squares is sum(2*old + 1) over the in-tile increments.
+        const unsigned m = tile[spill];
+        sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
+        unsigned long long hits = (unsigned long long)(visits - m);
+        unsigned long long sq = 2ull * sumold + hits;
         // block reduction of (S, hits, nlow)
         sq = wave_sum(sq);
         hits = wave_sum(hits);

@@ -123,6 +123,9 @@ def _load():
         "ecmd_autotune": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32, C.POINTER(SearchS), u32,
                            C.POINTER(TuningS), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_get_profile": ([vp, C.POINTER(ProfileS), C.c_int], C.c_int),
+        "ecmd_hot_pixel_filter": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, i32, i32, u32, vp, vp, vp, vp], C.c_int),
+        "ecmd_resample": ([vp, C.POINTER(Sensor), C.POINTER(Sensor), vp, vp, vp, vp, i32, f32, C.c_uint64, u32,
+                           vp, vp, vp, vp], C.c_int),
         "ecmd_cnn_create": ([vp, C.c_uint64, C.POINTER(vp)], C.c_int),
         "ecmd_cnn_destroy": ([vp], None),
         "ecmd_cnn_get_params": ([vp, vp], C.c_int),
@@ -382,6 +385,37 @@ class Context:
                                                     C.byref(sp), a.flags, out)
         self._check(rc, allow=(EBUDGET, EFRONTIER))
         return [Result.of(out[i]) for i in range(B)]
+
+    def _preproc_out(self, x, offsets):
+        n = int(offsets[-1] - offsets[0])
+        B = int(offsets.shape[0]) - 1
+        return (_empty_like(x, max(n, 1), np.float32), _empty_like(x, max(n, 1), np.float32),
+                _empty_like(x, max(n, 1), np.float32), _empty_like(x, B + 1, np.int64))
+
+    def hot_pixel_filter(self, sensor: Sensor, x, y, t_rel, offsets, max_count: int):
+        """Drop the events of pixels holding more than max_count events of
+        their window (Sec. 6 preprocessing); returns (x, y, t_rel, offsets)."""
+        a = _Args()
+        B = int(offsets.shape[0]) - 1
+        xo, yo, to, oo = self._preproc_out(x, offsets)
+        self._check(lib().ecmd_hot_pixel_filter(self.h, C.byref(sensor), a.ptr(x, np.float32), a.ptr(y, np.float32),
+                                                a.ptr(t_rel, np.float32), a.ptr(offsets, np.int64), B, int(max_count),
+                                                a.flags, a.ptr(xo, np.float32), a.ptr(yo, np.float32),
+                                                a.ptr(to, np.float32), a.ptr(oo, np.int64)))
+        m = int(oo[-1])
+        return xo[:m], yo[:m], to[:m], oo
+
+    def resample(self, in_sensor: Sensor, out_sensor: Sensor, x, y, t_rel, offsets, keep_frac: float, seed: int):
+        """Resized and resampled events (Sec. 6); returns (x, y, t_rel, offsets)."""
+        a = _Args()
+        B = int(offsets.shape[0]) - 1
+        xo, yo, to, oo = self._preproc_out(x, offsets)
+        self._check(lib().ecmd_resample(self.h, C.byref(in_sensor), C.byref(out_sensor), a.ptr(x, np.float32),
+                                        a.ptr(y, np.float32), a.ptr(t_rel, np.float32), a.ptr(offsets, np.int64), B,
+                                        float(keep_frac), C.c_uint64(seed), a.flags, a.ptr(xo, np.float32),
+                                        a.ptr(yo, np.float32), a.ptr(to, np.float32), a.ptr(oo, np.int64)))
+        m = int(oo[-1])
+        return xo[:m], yo[:m], to[:m], oo
 
     def downsample(self, sensor: Sensor, x, y, offsets):
         a = _Args()
