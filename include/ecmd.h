@@ -196,6 +196,15 @@ int ecmd_estimate_divergence_batched(ecmd_ctx *ctx, const ecmd_sensor *sensor,
                                      const ecmd_search *search, uint32_t flags,
                                      const float *d_seeds, ecmd_result *out);
 
+/* Stream estimation (Sec. 4.4): the events of [t_start, t_start + K tau)
+ * are cut into K consecutive windows [t_start + k tau, t_start + (k+1) tau)
+ * (half-open, fp64), each estimated as in the batched call (one launch
+ * sequence for all K windows); out[k] is window k's result.  events->t must
+ * be non-decreasing. */
+int ecmd_estimate_stream(ecmd_ctx *ctx, const ecmd_sensor *sensor, const ecmd_events *events,
+                         double t_start, double tau, int32_t K, const ecmd_search *search,
+                         uint32_t flags, ecmd_result *out);
+
 /* -------------------------------------------------------------- probes */
 
 /* Pixel index ky*W + kx of every event at divergence d (-1 = outside),

@@ -1101,6 +1101,71 @@ static int preproc_impl(ecmd_ctx* c, int kind, const ecmd_sensor* in_s, const ec
 
 extern "C" {
 
+int ecmd_estimate_stream(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_events* events, double t_start,
+                         double tau, int32_t K, const ecmd_search* search, uint32_t flags, ecmd_result* out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    if (!events || !out || K < 0 || K > 65535) return fail(c, ECMD_EINVAL, "bad stream arguments");
+    if (!isfinite(t_start) || !(tau > 0.0) || !isfinite(tau)) return fail(c, ECMD_EINVAL, "bad t_start or tau");
+    if (K == 0) return ECMD_OK;
+    const long long n = events->n;
+    if (n < 0 || (n > 0 && (!events->x || !events->y || !events->t))) return fail(c, ECMD_EINVAL, "bad events");
+    HIPCHK(c, hipSetDevice(c->device));
+    // window bounds and offsets on the device
+    const double* dt = events->t;
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        for (long long i = 1; i < n; ++i)
+            if (!(events->t[i] >= events->t[i - 1])) return fail(c, ECMD_EINVAL, "stream times must be sorted");
+        HIPCHK(c, c->counts.ensure(sizeof(double) * std::max(n, 1ll)));
+        if (n) HIPCHK(c, hipMemcpyAsync(c->counts.p, events->t, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        dt = (const double*)c->counts.p;
+    }
+    HIPCHK(c, c->misc.ensure(sizeof(long long) * (K + 1)));
+    long long* doff = c->misc.as<long long>();
+    HIPCHK(c, launch_stream_bounds(c->stream, dt, n, t_start, tau, K, doff));
+    std::vector<long long> off(K + 1);
+    HIPCHK(c, hipMemcpyAsync(off.data(), doff, sizeof(long long) * (K + 1), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const long long o0 = off[0], m = off[K] - off[0];
+    HIPCHK(c, c->keep.ensure(sizeof(float) * std::max(m, 1ll)));
+    float* trel = (float*)c->keep.p;
+    HIPCHK(c, launch_stream_trel(c->stream, dt, doff, m, K, t_start, tau, trel));
+    // batched estimation on the selected range (x, y staged to the device if needed)
+    std::vector<long long> rel(K + 1);
+    for (int k = 0; k <= K; ++k) rel[k] = off[k] - o0;
+    std::vector<float> taus(K, (float)tau);
+    const float *dx = events->x + o0, *dy = events->y + o0;
+    if (!(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->img.ensure(sizeof(float) * 2 * std::max(m, 1ll)));
+        float* sxy = c->img.as<float>();
+        dx = sxy;
+        dy = sxy + std::max(m, 1ll);
+        if (m) {
+            HIPCHK(c, hipMemcpyAsync((void*)dx, events->x + o0, sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync((void*)dy, events->y + o0, sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // offsets and tau are host values here; the events are on the device
+    int L = 0;
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    if ((rc = check_search(c, search, &L))) return rc;
+    if (!(search->d_hi * (float)tau < 1.0f)) return fail(c, ECMD_EINVAL, "d_hi * tau must be < 1 (cheirality)");
+    c->h_off = rel;
+    c->h_tau = taus;
+    Inputs in;
+    in.x = dx;
+    in.y = dy;
+    in.t = trel;
+    const void* p;
+    if ((rc = stage(c, c->soff, rel.data(), sizeof(long long) * (K + 1), 0, &p))) return rc;
+    in.off = (const long long*)p;
+    if ((rc = stage(c, c->stau, taus.data(), sizeof(float) * K, 0, &p))) return rc;
+    in.tau = (const float*)p;
+    return run_search(c, sensor, in, K, search, L, out);
+}
+
 int ecmd_hot_pixel_filter(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
                           const int64_t* offsets, int32_t B, int32_t max_count, uint32_t flags, float* x_out,
                           float* y_out, float* t_out, int64_t* offsets_out) {

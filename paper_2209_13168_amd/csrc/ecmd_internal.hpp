@@ -161,6 +161,11 @@ hipError_t launch_resample_keep(hipStream_t s, const long long* offsets, int B, 
 hipError_t launch_hot_keep(hipStream_t s, const float* x, const float* y, const long long* offsets, int B, long long n,
                            int W, int H, unsigned* counts, unsigned max_count, unsigned char* keep);
 
+hipError_t launch_stream_bounds(hipStream_t s, const double* t, long long n, double t_start, double tau, int K,
+                                long long* offsets);
+hipError_t launch_stream_trel(hipStream_t s, const double* t, const long long* offsets, long long n_sel, int K,
+                              double t_start, double tau, float* t_rel);
+
 // learned incumbent (ecmd_cnn.hip)
 size_t cnn_lds_bytes();
 int cnn_nparam();

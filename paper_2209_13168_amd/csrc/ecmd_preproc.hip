@@ -190,4 +190,48 @@ hipError_t launch_hot_keep(hipStream_t s, const float* x, const float* y, const 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ stream windows
+
+// offsets[k] = first event with t >= t_start + k * tau (t non-decreasing)
+__global__ void k_stream_bounds(const double* __restrict__ t, long long n, double t_start, double tau, int K,
+                                long long* __restrict__ offsets) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    const double b = t_start + (double)k * tau;
+    long long lo = 0, hi = n;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (t[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    offsets[k] = lo;
+}
+
+// t_rel of every event of the K windows, relative to its window start
+__global__ __launch_bounds__(kPreThreads) void k_stream_trel(const double* __restrict__ t,
+                                                            const long long* __restrict__ offsets, int K,
+                                                            double t_start, double tau, float* __restrict__ t_rel) {
+    const long long i = offsets[0] + (long long)blockIdx.x * kPreThreads + threadIdx.x;
+    if (i >= offsets[K]) return;
+    int lo = 0, hi = K;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offsets[mid] <= i) lo = mid; else hi = mid;
+    }
+    t_rel[i - offsets[0]] = (float)(t[i] - (t_start + (double)lo * tau));
+}
+
+hipError_t launch_stream_bounds(hipStream_t s, const double* t, long long n, double t_start, double tau, int K,
+                                long long* offsets) {
+    k_stream_bounds<<<(K + 1 + 255) / 256, 256, 0, s>>>(t, n, t_start, tau, K, offsets);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_trel(hipStream_t s, const double* t, const long long* offsets, long long n_sel, int K,
+                              double t_start, double tau, float* t_rel) {
+    if (n_sel <= 0) return hipSuccess;
+    k_stream_trel<<<(unsigned)((n_sel + kPreThreads - 1) / kPreThreads), kPreThreads, 0, s>>>(t, offsets, K, t_start,
+                                                                                             tau, t_rel);
+    return hipGetLastError();
+}
+
 }  // namespace ecmd

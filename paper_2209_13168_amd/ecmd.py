@@ -123,6 +123,8 @@ def _load():
         "ecmd_autotune": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32, C.POINTER(SearchS), u32,
                            C.POINTER(TuningS), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_get_profile": ([vp, C.POINTER(ProfileS), C.c_int], C.c_int),
+        "ecmd_estimate_stream": ([vp, C.POINTER(Sensor), C.POINTER(EventsS), C.c_double, C.c_double, i32,
+                                  C.POINTER(SearchS), u32, C.POINTER(ResultS)], C.c_int),
         "ecmd_hot_pixel_filter": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, i32, i32, u32, vp, vp, vp, vp], C.c_int),
         "ecmd_resample": ([vp, C.POINTER(Sensor), C.POINTER(Sensor), vp, vp, vp, vp, i32, f32, C.c_uint64, u32,
                            vp, vp, vp, vp], C.c_int),
@@ -385,6 +387,19 @@ class Context:
                                                     C.byref(sp), a.flags, out)
         self._check(rc, allow=(EBUDGET, EFRONTIER))
         return [Result.of(out[i]) for i in range(B)]
+
+    def estimate_stream(self, sensor: Sensor, x, y, t, t_start: float, tau: float, K: int, d_lo: float,
+                        d_hi: float, eps: float, **kw) -> list:
+        """K consecutive windows of length tau from t_start (Sec. 4.4)."""
+        a = _Args()
+        n = int(x.shape[0])
+        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n)
+        sp = _search(d_lo, d_hi, eps, **kw)
+        out = (ResultS * max(K, 1))()
+        rc = lib().ecmd_estimate_stream(self.h, C.byref(sensor), C.byref(ev), float(t_start), float(tau), int(K),
+                                        C.byref(sp), a.flags, out)
+        self._check(rc, allow=(EBUDGET, EFRONTIER))
+        return [Result.of(out[i]) for i in range(K)]
 
     def _preproc_out(self, x, offsets):
         n = int(offsets[-1] - offsets[0])

@@ -60,3 +60,32 @@ def test_resample_bit_exact_and_estimate(ctx, orc):
         o = orc.bnb(orc.Events(xo[oo[k]:oo[k + 1]], yo[oo[k]:oo[k + 1]], to[oo[k]:oo[k + 1]], s.tau, 160, 90,
                                (80.0, 45.0)), s.d_lo, s.d_hi, 1e-4)
         assert (r.j_star, r.K) == (o.j_star, o.K)
+
+
+def test_stream_windows_match_oracle(ctx, orc):
+    """Stream mode (Sec. 4.4): a descent recorded as one stream, cut into
+    consecutive windows; each window equals the oracle on the same events."""
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    ws = config_windows("c2", range(4), n_events=15_000)
+    s = ws[0].spec
+    tau = float(np.float32(s.tau))
+    t0 = 50.0
+    t = np.concatenate([t0 + k * tau + w.t_rel.astype(np.float64) for k, w in enumerate(ws)])
+    x = np.concatenate([w.x for w in ws])
+    y = np.concatenate([w.y for w in ws])
+    sen = ecmd.sensor(s.width, s.height, s.foe)
+    host = ctx.estimate_stream(sen, x, y, t, t0, tau, len(ws), s.d_lo, s.d_hi, 1e-4)
+    dev = torch.device("cuda:0")
+    devr = ctx.estimate_stream(sen, torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev),
+                               torch.from_numpy(t).to(dev), t0, tau, len(ws), s.d_lo, s.d_hi, 1e-4)
+    for k in range(len(ws)):
+        lo, hi = t0 + k * tau, t0 + (k + 1) * tau
+        sel = (t >= lo) & (t < hi)
+        tr = (t[sel] - lo).astype(np.float32)
+        o = orc.bnb(orc.Events(x[sel], y[sel], tr, tau, s.width, s.height, s.foe), s.d_lo, s.d_hi, 1e-4)
+        for r in (host[k], devr[k]):
+            assert r.status == 0 and (r.j_star, r.K) == (o.j_star, o.K)
+            assert r.n_events == int(sel.sum())
