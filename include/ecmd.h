@@ -153,19 +153,21 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
  * per window and step (0 = 64).  tile_px: largest image tile per LDS
  * histogram (0 = what the LDS holds; smaller values split the FOE quadrants
  * further, trading guest copies for occupancy).  graph: replay the step
- * loop as a captured hipGraph (0 = plain launches). */
+ * loop as a captured hipGraph (0 = plain launches).  group: hypotheses of
+ * one window and tile evaluated per work item (0 = chosen from the batch
+ * size: 1 for a single window, up to 8 for large batches). */
 typedef struct {
     int32_t frontier_batch;
     int32_t tile_px;
     int32_t graph;
-    int32_t reserved;
+    int32_t group;
 } ecmd_tuning;
 
 int ecmd_ctx_set_tuning(ecmd_ctx *ctx, const ecmd_tuning *tuning);
 int ecmd_ctx_get_tuning(const ecmd_ctx *ctx, ecmd_tuning *out);
 
 /* Autotuner: times candidate tunings (frontier batch, tile size, graph
- * replay) on the given batch (arguments as ecmd_estimate_divergence_batched,
+ * replay, hypotheses per item) on the given batch (arguments as ecmd_estimate_divergence_batched,
  * with search->frontier_batch ignored), keeps the fastest in the context and
  * writes it to `best`; ms_best (nullable) receives its time per call. */
 int ecmd_autotune(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x, const float *y,

@@ -84,7 +84,7 @@ struct ecmd_ctx {
     // prep
     DevBuf wp, blk, cnt_own, cnt_guest, seg_off, seg_own, cursor, ev, err_flag;
     // search
-    DevBuf state, front, sel, hyps, items, queues, part, n_active;
+    DevBuf state, front, sel, hyps, act, items, queues, part, n_active;
     // probes / window selection / downsample
     DevBuf pix, img, keep, counts, misc;
     HostBuf pinned;
@@ -380,10 +380,18 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     const int T = g.T;
+    // hypotheses per work item: enough items to fill the GPU, fewer set-ups
+    {
+        const long long work = (long long)B * sp.HS * T;
+        const long long slots = (long long)c->num_cu * 8;
+        sp.G = (int)std::max(1ll, std::min(8ll, work / std::max(slots, 1ll)));
+        if (c->tune.group > 0) sp.G = std::min(c->tune.group, 64);
+    }
     HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
     HIPCHK(c, c->front.ensure(sizeof(Node) * (size_t)B * sp.CAP));
     HIPCHK(c, c->sel.ensure(sizeof(Sel) * (size_t)B * sp.F));
     HIPCHK(c, c->hyps.ensure(sizeof(Hyp) * (size_t)B * sp.HS));
+    HIPCHK(c, c->act.ensure(sizeof(int) * (size_t)B * sp.HS));
     const int qcap = ((B + kXcd - 1) / kXcd) * sp.HS * T;  // windows w = r (mod kXcd) share queue r
     HIPCHK(c, c->items.ensure(sizeof(Item) * (size_t)kXcd * qcap));
     HIPCHK(c, c->queues.ensure(sizeof(Queue) * 2 * kXcd));
@@ -393,8 +401,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     HIPCHK(c, hipMemsetAsync(c->n_active.p, 0, sizeof(int), c->stream));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
-                          c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->items.as<Item>(), qcap, &q[0], T,
-                          c->seg_off.as<long long>()));
+                          c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(), qcap, &q[0],
+                          T, c->seg_off.as<long long>()));
     const size_t lds = eval_lds_bytes(g.max_tile_px);
     HIPCHK(c, eval_set_lds(lds));
     const int nb = eval_blocks(c, lds);
@@ -405,16 +413,16 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         for (int parity = 0; parity < 2; ++parity) {
             if (timed) tm.begin();
             hipError_t e = launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), qcap,
-                                       &q[parity * kXcd], &q[(1 - parity) * kXcd], c->part.as<Part>(), sp.HS,
-                                       nullptr);
+                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(),
+                                       c->items.as<Item>(), qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd],
+                                       c->part.as<Part>(), sp.HS, nullptr);
             if (e != hipSuccess) return e;
             if (timed) tm.end(0);
             if (timed) tm.begin();
             e = launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
                                 c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(), c->hyps.as<Hyp>(),
-                                c->part.as<Part>(), c->items.as<Item>(), qcap, &q[(1 - parity) * kXcd],
-                                c->n_active.as<int>());
+                                c->act.as<int>(), c->part.as<Part>(), c->items.as<Item>(), qcap,
+                                &q[(1 - parity) * kXcd], c->n_active.as<int>());
             if (e != hipSuccess) return e;
             if (timed) tm.end(1);
         }
@@ -428,7 +436,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
             const unsigned char* b = (const unsigned char*)p;
             key.insert(key.end(), b, b + n);
         };
-        void* ptrs[] = {c->ev.p, c->seg_off.p, c->seg_own.p, c->hyps.p, c->items.p, c->queues.p, c->part.p,
+        void* ptrs[] = {c->ev.p, c->seg_off.p, c->seg_own.p, c->hyps.p, c->act.p, c->items.p, c->queues.p, c->part.p,
                         c->wp.p, c->state.p, c->front.p, c->sel.p, c->n_active.p, (void*)c->stream};
         put(ptrs, sizeof ptrs);
         put(&g, sizeof g);
@@ -594,7 +602,7 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->sx, &c->sy, &c->st, &c->soff, &c->stau, &c->sseed, &c->wp, &c->blk, &c->cnt_own,
                       &c->cnt_guest, &c->seg_off, &c->seg_own, &c->cursor, &c->ev, &c->err_flag, &c->state,
-                      &c->front, &c->sel, &c->hyps, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
+                      &c->front, &c->sel, &c->hyps, &c->act, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
                       &c->img, &c->keep, &c->counts, &c->misc};
     for (DevBuf* b : bufs) b->release();
     c->pinned.release();
@@ -608,7 +616,7 @@ const char* ecmd_last_error(const ecmd_ctx* c) { return c ? c->err.c_str() : "NU
 
 int ecmd_ctx_set_tuning(ecmd_ctx* c, const ecmd_tuning* t) {
     if (!c || !t) return ECMD_EINVAL;
-    if (t->frontier_batch < 0 || t->frontier_batch > 1024 || t->tile_px < 0)
+    if (t->frontier_batch < 0 || t->frontier_batch > 1024 || t->tile_px < 0 || t->group < 0 || t->group > 64)
         return fail(c, ECMD_EINVAL, "tuning out of range");
     c->tune = *t;
     return ECMD_OK;
@@ -639,10 +647,12 @@ int ecmd_autotune(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const 
     for (int ti = 0; ti < 3; ++ti) {
         if (ti > 0 && (long long)sensor->width * sensor->height <= tiles[ti]) break;  // one tile already
         for (int F : Fs) {
-            for (int gr = 0; gr < 2; ++gr) {
+            for (int gv = 0; gv < 4; ++gv) {
+                const int groups[] = {0, 1, 4, 0};
                 c->tune.frontier_batch = F;
                 c->tune.tile_px = ti == 0 ? 0 : tiles[ti];
-                c->tune.graph = gr;
+                c->tune.graph = gv == 3 ? 1 : 0;
+                c->tune.group = groups[gv];
                 double ms = 1e300;
                 for (int rep = 0; rep < 3; ++rep) {
                     auto t0 = std::chrono::steady_clock::now();
@@ -858,8 +868,12 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     // every hypothesis on every tile
     std::vector<Item> items((size_t)m * T);
     for (int h = 0; h < m; ++h)
-        for (int t = 0; t < T; ++t) items[(size_t)h * T + t] = Item{h, t};
+        for (int t = 0; t < T; ++t) items[(size_t)h * T + t] = Item{0, t, h, 1};
     HIPCHK(c, c->items.ensure(sizeof(Item) * items.size()));
+    std::vector<int> ident(m);
+    for (int h = 0; h < m; ++h) ident[h] = h;
+    HIPCHK(c, c->act.ensure(sizeof(int) * m));
+    HIPCHK(c, hipMemcpyAsync(c->act.p, ident.data(), sizeof(int) * m, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->items.p, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice,
                              c->stream));
     Queue hq[2 * kXcd] = {};
@@ -880,8 +894,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     HIPCHK(c, eval_set_lds(lds));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_eval(c->stream, g, eval_blocks(c, lds), lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->items.as<Item>(), (int)items.size(), &q[0],
-                          &q[kXcd], c->part.as<Part>(), m, dimg));
+                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(),
+                          (int)items.size(), &q[0], &q[kXcd], c->part.as<Part>(), m, dimg));
     std::vector<Part> parts(items.size());
     std::vector<long long> seg(T + 1);
     HIPCHK(c, hipMemcpyAsync(parts.data(), c->part.p, sizeof(Part) * parts.size(), hipMemcpyDeviceToHost,

@@ -74,6 +74,7 @@ struct Search {
     int F;    // nodes expanded together per step
     int CAP;  // frontier capacity per window
     int HS;   // hypothesis slots per window (3F)
+    int G;    // hypotheses per work item
     long long max_nodes;
     long long gamma_key;  // stop when best K_bar - K_inc <= gamma_key (-1: gamma = 0)
     long long M;          // pixels
@@ -96,9 +97,14 @@ struct WinState {
     long long event_hyp, pixel_updates;
 };
 
+// A work item: tile t of window w for the hypotheses act[w * HS + r0 + k],
+// k < cnt (a group of consecutive active slots, evaluated one after another
+// by one workgroup so that the item's set-up is paid once per group).
 struct Item {
-    int wh;  // window * HS + slot
-    int t;   // tile
+    int w;
+    int t;
+    int r0;
+    int cnt;
 };
 
 // Work queues: one per XCD (workgroups are dispatched to the 8 XCDs in
@@ -126,16 +132,16 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
                        unsigned long long* cursor, float4* ev, int* err_flag);
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
-                       WinState* st, Sel* sel, Hyp* hyps, Item* items, int qcap, Queue* q, int T,
+                       WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off);
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
-                           const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
+                           const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active);
 // q, q_reset: kXcd queues each
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes,
                        const float4* ev, const long long* seg_off, const int* seg_own,
-                       const Hyp* hyps, const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part,
-                       int HS, unsigned* img_out);
+                       const Hyp* hyps, const int* act, const Item* items, int qcap, Queue* q, Queue* q_reset,
+                       Part* part, int HS, unsigned* img_out);
 hipError_t launch_rates(hipStream_t s, const float* d_a, const float* d_b, int m, float tau, Hyp* hyps);
 hipError_t launch_probe_pixels(hipStream_t s, const float* x, const float* y, const float* t_rel,
                                long long n, float tau, float d, int W, int H, float cx, float cy,

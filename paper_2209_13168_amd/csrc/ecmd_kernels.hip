@@ -362,9 +362,9 @@ size_t eval_lds_bytes(int max_tile_px) {
 // so the sum of squares is sum(2*old + 1) with no pass over the tile.
 __global__ __launch_bounds__(kEvalThreads) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
-    const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const Item* __restrict__ items, int qcap,
-    Queue* __restrict__ q, Queue* __restrict__ q_reset, Part* __restrict__ part, int HS,
-    unsigned* __restrict__ img_out) {
+    const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const int* __restrict__ act,
+    const Item* __restrict__ items, int qcap, Queue* __restrict__ q, Queue* __restrict__ q_reset,
+    Part* __restrict__ part, int HS, unsigned* __restrict__ img_out) {
     extern __shared__ unsigned smem[];
     const int tid = threadIdx.x;
     unsigned* const tile = smem;
@@ -378,15 +378,20 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     const float Wf = (float)g.W, Hf = (float)g.H;
     const int home = blockIdx.x % kXcd;
     int qi = 0;  // queues tried so far, starting at this XCD's own (thread 0 only)
+    int qn[kXcd];  // queue sizes, read once (thread 0 only)
+    if (tid == 0)
+        for (int r = 0; r < kXcd; ++r) qn[r] = q[(home + r) % kXcd].n_items;
     for (;;) {
         if (tid == 0) {
             int got = -1;
             while (qi < kXcd) {
                 const int r = (home + qi) % kXcd;
-                const int k = atomicAdd(&q[r].next, 1);
-                if (k < q[r].n_items) {
-                    got = r * qcap + k;
-                    break;
+                if (qn[qi] > 0) {
+                    const int k = atomicAdd(&q[r].next, 1);
+                    if (k < qn[qi]) {
+                        got = r * qcap + k;
+                        break;
+                    }
                 }
                 ++qi;
             }
@@ -397,8 +402,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         __syncthreads();
         if (it < 0) break;
         const Item item = items[it];
-        const int w = item.wh / HS, t = item.t;
-        const Hyp hp = hyps[item.wh];
+        const int w = item.w, t = item.t;
         const int tx = t % g.ntx, ty = t / g.ntx;
         const int x0 = g.colcut[tx], y0 = g.rowcut[ty];
         const unsigned tw = (unsigned)(g.colcut[tx + 1] - x0), th = (unsigned)(g.rowcut[ty + 1] - y0);
@@ -407,6 +411,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const long long seg = (long long)w * g.T + t;
         const long long beg = seg_off[seg], end = seg_off[seg + 1];
         const long long own_end = beg + seg_own[seg];
+      for (int gk = 0; gk < item.cnt; ++gk) {
+        const int wh = w * HS + act[w * HS + item.r0 + gk];
+        const Hyp hp = hyps[wh];
 
         for (int i = tid; i < npx + kEvalThreads; i += kEvalThreads) tile[i] = 0u;
         __syncthreads();
@@ -497,15 +504,17 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             pt.N = (long long)(hp.kind == HYP_POINT ? b : c);
             pt.U = b;
             pt.pad = 0;
-            part[(long long)item.wh * g.T + t] = pt;
+            part[(long long)wh * g.T + t] = pt;
         }
         if (img_out) {
             const long long M = (long long)g.W * g.H;
             for (int k = tid; k < npx; k += kEvalThreads) {
                 int lx = k % (int)tw, ly = k / (int)tw;
-                img_out[(long long)item.wh * M + (long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
+                img_out[(long long)wh * M + (long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
             }
         }
+        __syncthreads();  // the tile is cleared again for the next hypothesis
+      }
     }
 }
 
@@ -518,10 +527,11 @@ hipError_t eval_set_lds(size_t bytes) {
 }
 
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes, const float4* ev,
-                       const long long* seg_off, const int* seg_own, const Hyp* hyps, const Item* items,
-                       int qcap, Queue* q, Queue* q_reset, Part* part, int HS, unsigned* img_out) {
-    k_eval<<<nblocks, kEvalThreads, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, items, qcap, q, q_reset, part,
-                                                   HS, img_out);
+                       const long long* seg_off, const int* seg_own, const Hyp* hyps, const int* act,
+                       const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part, int HS,
+                       unsigned* img_out) {
+    k_eval<<<nblocks, kEvalThreads, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
+                                                   part, HS, img_out);
     return hipGetLastError();
 }
 
@@ -590,14 +600,16 @@ __device__ __forceinline__ void slot_sums(const Part* pw, int slot, int T, const
     }
 }
 
-// Hypotheses of the selected nodes and their work items.
+// Hypotheses of the selected nodes, the list of active slots, and the work
+// items: groups of up to G active slots on each non-empty tile, tile-major.
 __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
-                          const Sel* sl, int n_sel, Hyp* hy, Item* items, int qcap, Queue* qf, int* s_wave) {
+                          const Sel* sl, int n_sel, Hyp* hy, int* act, Item* items, int qcap, Queue* qf,
+                          int* s_wave) {
+    const int F = sp.F, HS = sp.HS, G = sp.G;
     const int qr = w % kXcd;  // this window's queue
     Item* qitems = items + (long long)qr * qcap;
-    const int F = sp.F, HS = sp.HS;
     __shared__ int s_base;
-    // slots with work: points [0, n_sel), intervals F + [0, 2 n_sel) of nodes with children
+    int na = 0;  // active slots so far
     for (int h0 = 0; h0 < HS; h0 += NTF) {
         const int h = h0 + threadIdx.x;
         Hyp hp;
@@ -622,17 +634,22 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
         if (h < HS) hy[h] = hp;
         int tot;
         const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
-        if (threadIdx.x == 0) s_base = (tot * nt) ? atomicAdd(&qf[qr].n_items, tot * nt) : 0;
-        __syncthreads();
-        if (hp.kind != HYP_NONE)
-            for (int k = 0; k < nt; ++k) {  // tile-major: items sharing events are adjacent
-                Item it;
-                it.wh = w * HS + h;
-                it.t = tiles[k];
-                qitems[s_base + k * tot + r] = it;
-            }
-        __syncthreads();
+        if (hp.kind != HYP_NONE) act[na + r] = h;
+        na += tot;
     }
+    const int ng = (na + G - 1) / G;
+    if (threadIdx.x == 0) s_base = (ng * nt) ? atomicAdd(&qf[qr].n_items, ng * nt) : 0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < ng * nt; k += NTF) {
+        const int ti = k / ng, gi = k % ng;  // tile-major: items sharing events are adjacent
+        Item it;
+        it.w = w;
+        it.t = tiles[ti];
+        it.r0 = gi * G;
+        it.cnt = min(G, na - gi * G);
+        qitems[s_base + k] = it;
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ void nonempty_tiles(int w, int T, const long long* seg_off, int* tiles, int* s_nt,
@@ -652,7 +669,7 @@ __device__ __forceinline__ void nonempty_tiles(int w, int T, const long long* se
 
 __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restrict__ wp,
                                               const float* __restrict__ seeds, int B, WinState* __restrict__ st,
-                                              Sel* __restrict__ sel, Hyp* __restrict__ hyps,
+                                              Sel* __restrict__ sel, Hyp* __restrict__ hyps, int* __restrict__ act,
                                               Item* __restrict__ items, int qcap, Queue* __restrict__ q, int T,
                                               const long long* __restrict__ seg_off) {
     const int w = blockIdx.x;
@@ -697,14 +714,15 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
     }
     __syncthreads();
     nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
-    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, items, qcap, q, s_wave);
+    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, act + (long long)w * sp.HS,
+              items, qcap, q, s_wave);
 }
 
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
-                       WinState* st, Sel* sel, Hyp* hyps, Item* items, int qcap, Queue* q, int T,
+                       WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off) {
     if (B <= 0) return hipSuccess;
-    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, items, qcap, q, T, seg_off);
+    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, act, items, qcap, q, T, seg_off);
     return hipGetLastError();
 }
 
@@ -716,8 +734,8 @@ hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, cons
 __global__ __launch_bounds__(NTF) void k_frontier(
     Search sp, const WinParam* __restrict__ wp, int B, int T, const long long* __restrict__ seg_off,
     WinState* __restrict__ st, Node* __restrict__ front, Sel* __restrict__ sel, Hyp* __restrict__ hyps,
-    const Part* __restrict__ part, Item* __restrict__ items, int qcap, Queue* __restrict__ qf,
-    int* __restrict__ n_active) {
+    int* __restrict__ act, const Part* __restrict__ part, Item* __restrict__ items, int qcap,
+    Queue* __restrict__ qf, int* __restrict__ n_active) {
     const int w = blockIdx.x, tid = threadIdx.x;
     __shared__ WinState s;
     __shared__ long long s_hi[NTF];
@@ -914,14 +932,15 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s.steps += 1;
         st[w] = s;
     }
-    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, items, qcap, qf, s_wave);
+    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, act + (long long)w * HS, items, qcap, qf,
+              s_wave);
 }
 
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
-                           const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps,
+                           const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active) {
     if (B <= 0) return hipSuccess;
-    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, part, items, qcap, q_fill,
+    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, act, part, items, qcap, q_fill,
                                 n_active);
     return hipGetLastError();
 }

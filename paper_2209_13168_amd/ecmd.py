@@ -61,7 +61,7 @@ class ResultS(C.Structure):
 
 class TuningS(C.Structure):
     _fields_ = [("frontier_batch", C.c_int32), ("tile_px", C.c_int32), ("graph", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("group", C.c_int32)]
 
 
 class ProfileS(C.Structure):
@@ -247,14 +247,14 @@ class Context:
     def last_error(self) -> str:
         return lib().ecmd_last_error(self.h).decode()
 
-    def set_tuning(self, frontier_batch: int = 0, tile_px: int = 0, graph: bool = False):
-        t = TuningS(int(frontier_batch), int(tile_px), 1 if graph else 0, 0)
+    def set_tuning(self, frontier_batch: int = 0, tile_px: int = 0, graph: bool = False, group: int = 0):
+        t = TuningS(int(frontier_batch), int(tile_px), 1 if graph else 0, int(group))
         self._check(lib().ecmd_ctx_set_tuning(self.h, C.byref(t)))
 
     def tuning(self) -> dict:
         t = TuningS()
         self._check(lib().ecmd_ctx_get_tuning(self.h, C.byref(t)))
-        return {"frontier_batch": t.frontier_batch, "tile_px": t.tile_px, "graph": bool(t.graph)}
+        return {"frontier_batch": t.frontier_batch, "tile_px": t.tile_px, "graph": bool(t.graph), "group": t.group}
 
     def autotune(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float, eps: float,
                  cache: Optional[str] = None) -> dict:
@@ -272,7 +272,7 @@ class Context:
             with open(cache) as f:
                 known = json.load(f)
             if key in known:
-                self.set_tuning(**{k: known[key][k] for k in ("frontier_batch", "tile_px", "graph")})
+                self.set_tuning(**{k: known[key][k] for k in ("frontier_batch", "tile_px", "graph", "group")})
                 return dict(known[key], cached=True)
         a = _Args()
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
@@ -283,7 +283,7 @@ class Context:
         self._check(lib().ecmd_autotune(self.h, C.byref(sensor), px, py, pt, po, ptau, B, C.byref(sp), a.flags,
                                         C.byref(best), C.byref(ms)))
         out = {"frontier_batch": best.frontier_batch, "tile_px": best.tile_px, "graph": bool(best.graph),
-               "ms": ms.value}
+               "group": best.group, "ms": ms.value}
         if cache:
             known = {}
             if os.path.exists(cache):

@@ -265,9 +265,9 @@ def test_graph_replay_and_tunings_match(ctx, orc):
     want = [orc.bnb(orc.Events.of_window(w), s.d_lo, s.d_hi, 1e-4) for w in ws]
     saved = ctx.tuning()
     try:
-        for F, tile, graph in [(64, 0, True), (16, 0, True), (64, 11000, False), (128, 6000, True),
-                               (64, 0, False), (64, 0, True)]:
-            ctx.set_tuning(F, tile, graph)
+        for F, tile, graph, group in [(64, 0, True, 0), (16, 0, True, 3), (64, 11000, False, 0),
+                                      (128, 6000, True, 8), (64, 0, False, 1), (64, 0, True, 0)]:
+            ctx.set_tuning(F, tile, graph, group)
             for _ in range(2):
                 got = ctx.estimate_batched(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
                 for r, o in zip(got, want):
