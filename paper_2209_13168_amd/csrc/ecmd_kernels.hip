@@ -37,7 +37,7 @@ __device__ __forceinline__ int cvt_flr(float v) {
 // floor of v clamped to [-1, hi]: -1 and hi both mean "outside the image"
 // (floor commutes with clamping to integer limits).
 __device__ __forceinline__ int flr_clamp(float v, int hi) {
-    return min(max(cvt_flr(v), -1), hi);
+    return cvt_flr(__builtin_amdgcn_fmed3f(v, -1.0f, (float)hi));
 }
 
 __device__ __forceinline__ i128 mk128(long long hi, unsigned long long lo) {
@@ -420,17 +420,20 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
 
         unsigned long long sumold = 0, nlow = 0;
         unsigned visits = 0;
+        // the segment's events, indexed from its start with 32-bit offsets
+        const float4* __restrict__ sev = ev + beg;
+        const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
             // flight, loads first, then U increments without branches.
             const float r = hp.ra;
             constexpr int U = 4;
-            constexpr long long S = kEvalThreads;
-            long long i = beg + tid;
-            for (; i + (U - 1) * S < end; i += U * S) {
+            constexpr unsigned S = kEvalThreads;
+            unsigned i = tid;
+            for (; i + (U - 1) * S < nseg; i += U * S) {
                 float4 e[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) e[k] = ev[i + k * S];
+                for (int k = 0; k < U; ++k) e[k] = sev[i + k * S];
                 unsigned a[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
@@ -445,8 +448,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 for (int k = 0; k < U; ++k) sumold += old[k];
                 visits += U;
             }
-            for (; i < end; i += S) {
-                const float4 e = ev[i];
+            for (; i < nseg; i += S) {
+                const float4 e = sev[i];
                 const unsigned lx = (unsigned)(cvt_flr(fmaf(e.z, r, e.x)) - x0);
                 const unsigned ly = (unsigned)(cvt_flr(fmaf(e.w, r, e.y)) - y0);
                 const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
@@ -457,14 +460,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
             WalkAcc acc{0ull, 0u, 0u};
-            long long i = beg + tid;
-            float4 e = i < end ? ev[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            for (; i < end; i += kEvalThreads) {
-                const long long inext = i + kEvalThreads;
-                const float4 en = inext < end ? ev[inext] : e;  // prefetch while walking
+            unsigned i = tid;
+            float4 e = sev[min(i, nseg - 1)];
+            for (; i < nseg; i += kEvalThreads) {
+                const float4 en = sev[min(i + kEvalThreads, nseg - 1)];  // prefetch while walking
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
-                if (i < own_end && inside(xa, ya, Wf, Hf) && inside(xb, yb, Wf, Hf)) nlow += 1;
+                nlow += (i < nown) & inside(xa, ya, Wf, Hf) & inside(xb, yb, Wf, Hf);
                 const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
                 tile_add(tile, spill, x0, y0, tw, th, kxa, kya, acc);
