@@ -77,7 +77,10 @@ typedef struct {
     double t0, t1;
 } ecmd_window;
 
-/* Search: d in [d_lo, d_hi] with grid spacing <= eps (0 <= d_lo < d_hi,
+/* A window holds fewer than 2^28 events (ECMD_EINVAL otherwise), and
+ * n^2 * 2 * (width + height + 3) < 9e18 so that the exact sums fit 64 bits.
+ *
+ * Search: d in [d_lo, d_hi] with grid spacing <= eps (0 <= d_lo < d_hi,
  * float(d_hi * tau) < 1: the cheirality limit of eq. (11)).  gamma > 0 stops
  * Algorithm 1 once the best bound is within gamma of the incumbent in
  * contrast units.  max_nodes > 0 caps node expansions (ECMD_EBUDGET).

@@ -534,7 +534,7 @@ static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, 
     for (int w = 0; w < B; ++w) {
         long long n = c->h_off[w + 1] - c->h_off[w];
         if (n < 0) return fail(c, ECMD_EINVAL, "offsets decrease at window %d", w);
-        if (n > (1ll << 31) - 1) return fail(c, ECMD_EINVAL, "window %d has too many events", w);
+        if (n >= kMaxWindowEvents) return fail(c, ECMD_EINVAL, "window %d has too many events (limit 2^28 - 1)", w);
         double bound = (double)n * (double)n * 2.0 * ((double)sensor->width + sensor->height + 3.0);
         if (bound >= 9.0e18) return fail(c, ECMD_EINVAL, "window %d: sums would overflow 64 bits", w);
         float t = c->h_tau[w];
@@ -775,7 +775,7 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
         if (!(tau > 0.0f)) return fail(c, ECMD_EINVAL, "window too short");
         if (!(search->d_hi * tau < 1.0f)) return fail(c, ECMD_EINVAL, "d_hi * tau must be < 1 (cheirality)");
         double bound = (double)m * (double)m * 2.0 * ((double)sensor->width + sensor->height + 3.0);
-        if (bound >= 9.0e18 || m > (1ll << 31) - 1) return fail(c, ECMD_EINVAL, "window has too many events");
+        if (bound >= 9.0e18 || m >= kMaxWindowEvents) return fail(c, ECMD_EINVAL, "window has too many events");
         Inputs in;
         in.x = dx;
         in.y = dy;

@@ -111,6 +111,9 @@ struct Item {
 // round-robin order of their index), so that the items of a window are
 // evaluated on one XCD and its events stay in that XCD's L2.  Queue r owns
 // the item slots [r * qcap, (r + 1) * qcap).
+// Events per window stay below 2^28, so every event of a (window, tile)
+// segment is reached with a 32-bit byte offset from the segment start.
+constexpr long long kMaxWindowEvents = 1ll << 28;
 constexpr int kXcd = 8;
 
 struct Queue {

@@ -421,7 +421,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         unsigned long long sumold = 0, nlow = 0;
         unsigned visits = 0;
         // the segment's events, indexed from its start with 32-bit offsets
-        const float4* __restrict__ sev = ev + beg;
+        // (byte offsets fit 32 bits: a segment holds fewer than 2^28 events)
+        const char* __restrict__ sev = reinterpret_cast<const char*>(ev + beg);
+        const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
         const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
@@ -433,7 +435,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             for (; i + (U - 1) * S < nseg; i += U * S) {
                 float4 e[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) e[k] = sev[i + k * S];
+                for (int k = 0; k < U; ++k) e[k] = at(i + k * S);
                 unsigned a[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 visits += U;
             }
             for (; i < nseg; i += S) {
-                const float4 e = sev[i];
+                const float4 e = at(i);
                 const unsigned lx = (unsigned)(cvt_flr(fmaf(e.z, r, e.x)) - x0);
                 const unsigned ly = (unsigned)(cvt_flr(fmaf(e.w, r, e.y)) - y0);
                 const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
@@ -461,9 +463,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             const float ra = hp.ra, rb = hp.rb;
             WalkAcc acc{0ull, 0u, 0u};
             unsigned i = tid;
-            float4 e = sev[min(i, nseg - 1)];
+            float4 e = at(min(i, nseg - 1));
             for (; i < nseg; i += kEvalThreads) {
-                const float4 en = sev[min(i + kEvalThreads, nseg - 1)];  // prefetch while walking
+                const float4 en = at(min(i + kEvalThreads, nseg - 1));  // prefetch while walking
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
                 nlow += (i < nown) & inside(xa, ya, Wf, Hf) & inside(xb, yb, Wf, Hf);
