@@ -10,9 +10,10 @@ event binning, point and interval evaluations, and the device frontier.
 Inputs are resident in HBM before the timed region starts.
 
 Printed: one JSON line with event-hypothesis evaluations per second (value),
-certified windows per second (batched, and plain one-window calls), the
-roofline of the hypothesis-evaluation kernel and the CPU oracle timed on a
-bounded sample of the same windows on this host.
+certified windows per second (batched; batched and seeded by the learned
+proposal when its weights are present; plain one-window calls), the roofline
+of the hypothesis-evaluation kernel and the CPU oracle timed on a bounded
+sample of the same windows on this host.
 """
 
 from __future__ import annotations
@@ -35,6 +36,44 @@ OPS_INTERVAL = 16  # per event and interval: 2 endpoint warps (4 fma, 4 floor), 
 OPS_PIXEL = 12     # per upper-bound pixel increment: corner test (7 fp64), 1 step, 2 range tests, 1 index, 1 acc
 # Peak lane-operation rate: 256 CUs x 64 lanes per clock (4 SIMDs x 16) x 2.4 GHz.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Bytes of one prepared event record read by the evaluation kernel (x, y, ax, ay as fp32).
+EVENT_RECORD_BYTES = 16
+
+# HBM traffic of the evaluation kernel per launch, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the
+# dispatches) of `bench.py --steps 2 --warmup 1 --plain-windows 0
+# --no-cpu-baseline` on the default workload, each scaled by bytes/KiB that
+# the same counter reads for a plain copy of 1 GiB (`bench.py
+# --calibrate-copy`).  The figures hold only for the kernel sources and the
+# workload they were taken on; for anything else `traffic` is null.
+TRAFFIC = {
+    "sources_sha256": None,
+    "workload": None,
+    "fetch_kib": None,
+    "write_kib": None,
+    "fetch_bytes_per_kib": None,
+    "write_bytes_per_kib": None,
+}
+KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
+                  "paper_2209_13168_amd/csrc/ecmd_api.hip")
+
+
+def sources_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(workload: dict):
+    """HBM bytes per evaluation launch from the recorded counters, or None."""
+    if TRAFFIC["sources_sha256"] != sources_sha256() or TRAFFIC["workload"] != workload:
+        return None
+    return round(TRAFFIC["fetch_kib"] * TRAFFIC["fetch_bytes_per_kib"]
+                 + TRAFFIC["write_kib"] * TRAFFIC["write_bytes_per_kib"])
 
 
 def parse():
@@ -45,11 +84,12 @@ def parse():
     ap.add_argument("--windows", type=int, default=32, help="windows per step")
     ap.add_argument("--frontier-batch", type=int, default=0)
     ap.add_argument("--plain-windows", type=int, default=8, help="windows timed one call each")
-    ap.add_argument("--cpu-windows", type=int, default=3, help="oracle sample size (windows)")
+    ap.add_argument("--cpu-windows", type=int, default=8, help="oracle sample size (windows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
                     help="trained proposal network (the step seeds the search with it when present)")
     ap.add_argument("--plain", action="store_true", help="time the search without the learned seeds")
+    ap.add_argument("--print-sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer three times (to scale HBM byte counters)")
     return ap.parse_args()
@@ -57,6 +97,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.print_sources_sha:
+        print(sources_sha256())
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the estimator has no multi-GPU path in this build "
@@ -99,7 +142,7 @@ def main():
     def step_learned():
         return ctx.estimate_learned(net, sensor, dx, dy, dt, doff, dtau, s.d_lo, s.d_hi, s.eps, **kw)
 
-    step = step_learned if net is not None else step_plain
+    step = step_plain
 
     ref = None
     for _ in range(args.warmup):
@@ -127,19 +170,19 @@ def main():
     pix = sum(r.pixel_updates for r in last)
     value = ev_hyp / sec
 
-    # batched without the learned seeds (same timing method, fewer steps)
-    batched_plain_ws = None
+    # batched and seeded by the learned proposal (same timing method, fewer steps)
+    learned_ws = nodes_learned = None
     if net is not None:
-        step_plain()
+        step_learned()
         torch.cuda.synchronize()
         a0 = time.perf_counter()
         reps = max(3, args.steps // 4)
         for _ in range(reps):
-            rp = step_plain()
+            rl = step_learned()
         torch.cuda.synchronize()
-        batched_plain_ws = B * reps / (time.perf_counter() - a0)
-        assert [(r.j_star, r.K) for r in rp] == [(r.j_star, r.K) for r in last]
-        nodes_plain = float(np.mean([r.nodes_expanded for r in rp]))
+        learned_ws = B * reps / (time.perf_counter() - a0)
+        assert [(r.j_star, r.K) for r in rl] == [(r.j_star, r.K) for r in last]
+        nodes_learned = float(np.mean([r.nodes_expanded for r in rl]))
 
     # plain: one window per call, no batching
     P = min(args.plain_windows, B)
@@ -161,13 +204,18 @@ def main():
     avg_launch_s = prof["eval_ms"] / 1e3 / launches
     ops_launch = ops_step * args.steps / launches
     achieved = ops_launch / avg_launch_s if avg_launch_s > 0 else 0.0
+    # each launch must read every event of every window still searching once
+    alg_bytes = EVENT_RECORD_BYTES * sum(r.steps * r.n_events for r in last) * args.steps / launches
+    tkey = {"windows": B, "frontier_batch": args.frontier_batch or 64}
     roof = {
         "bound": "alu",
         "achieved": round(achieved / 1e9, 1),
         "peak": round(PEAK_LANE_OPS / 1e9, 1),
         "unit": "Gop/s (VALU lane-ops)",
         "frac": round(achieved / PEAK_LANE_OPS, 4),
-        "traffic": None,
+        "traffic": traffic_per_launch(tkey),
+        "traffic_unit": "HBM bytes per launch",
+        "algorithmic_bytes": round(alg_bytes),
         "kernel": "k_eval",
         "avg_launch_us": round(avg_launch_s * 1e6, 2),
         "launches_per_step": round(launches / args.steps, 2),
@@ -191,22 +239,20 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{B} windows of the 346x260 config per step: 100k events/0.25 s window, "
-                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB"
-                        + (" seeded by the learned proposal" if net is not None else ""),
+                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB",
             "windows_per_step": B,
             "events_per_window": int(n_w.mean()),
             "eps": s.eps,
             "frontier_batch": args.frontier_batch or 64,
         },
         "windows_per_s": {
-            ("batched_learned" if net is not None else "batched"): round(B / sec, 2),
-            "batched": round(batched_plain_ws, 2) if batched_plain_ws else round(B / sec, 2),
+            "batched": round(B / sec, 2),
+            "batched_learned": round(learned_ws, 2) if learned_ws else None,
             "plain_one_window_per_call": round(P / sum(plain_t), 2) if plain_t else None,
         },
         "search": {
             "nodes_expanded_mean": float(np.mean([r.nodes_expanded for r in last])),
-            "nodes_expanded_mean_without_seeds": nodes_plain if net is not None else None,
-            "learned_seeds": net is not None,
+            "nodes_expanded_mean_learned_seeds": nodes_learned,
             "steps_max": int(max(r.steps for r in last)),
             "point_event_evals": int(pt_ev),
             "interval_event_evals": int(bd_ev),

@@ -79,6 +79,8 @@ struct ecmd_ctx {
     std::string err;
     int num_cu = 0;
     size_t max_lds = 0;
+    size_t eval_lds = 0;   // LDS bytes of the last evaluation set-up (0 = none yet)
+    int eval_nb = 0;       // evaluation workgroups for that size
     // staging of host inputs
     DevBuf sx, sy, st, soff, stau, sseed;
     // prep
@@ -346,10 +348,21 @@ static int tile_budget(ecmd_ctx* c) {
     return px;
 }
 
-static int eval_blocks(ecmd_ctx* c, size_t lds) {
-    int per_cu = 0;
-    if (eval_occupancy(&per_cu, lds) != hipSuccess || per_cu < 1) per_cu = 1;
-    return c->num_cu * std::min(per_cu, 4);
+// Persistent workgroup count of the evaluation kernel for `lds` bytes of
+// LDS: as many as fit at once, at most 4 per CU.  The kernel's dynamic LDS
+// limit is raised to the device maximum once per context, so that every
+// context's launches fit whatever another context set.
+static hipError_t eval_setup(ecmd_ctx* c, size_t lds, int* nb) {
+    if (c->eval_lds != lds) {
+        hipError_t e = eval_set_lds(c->max_lds);
+        if (e != hipSuccess) return e;
+        int per_cu = 0;
+        if (eval_occupancy(&per_cu, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+        c->eval_lds = lds;
+        c->eval_nb = c->num_cu * std::min(per_cu, 4);
+    }
+    *nb = c->eval_nb;
+    return hipSuccess;
 }
 
 // Whole batched search on staged inputs; fills out[0..B).
@@ -404,8 +417,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
                           c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(), qcap, &q[0],
                           T, c->seg_off.as<long long>()));
     const size_t lds = eval_lds_bytes(g.max_tile_px);
-    HIPCHK(c, eval_set_lds(lds));
-    const int nb = eval_blocks(c, lds);
+    int nb = 0;
+    HIPCHK(c, eval_setup(c, lds, &nb));
     int* h_active = (int*)c->pinned.p;
     int active = B;
     auto step_pair = [&](bool timed) -> hipError_t {
@@ -891,9 +904,10 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
         }
     }
     const size_t lds = eval_lds_bytes(g.max_tile_px);
-    HIPCHK(c, eval_set_lds(lds));
+    int nb = 0;
+    HIPCHK(c, eval_setup(c, lds, &nb));
     Queue* q = c->queues.as<Queue>();
-    HIPCHK(c, launch_eval(c->stream, g, eval_blocks(c, lds), lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+    HIPCHK(c, launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
                           c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(),
                           (int)items.size(), &q[0], &q[kXcd], c->part.as<Part>(), m, dimg));
     std::vector<Part> parts(items.size());
