@@ -19,6 +19,7 @@ sample of the same windows on this host.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -47,12 +48,12 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": None,
-    "workload": None,
-    "fetch_kib": None,
-    "write_kib": None,
-    "fetch_bytes_per_kib": None,
-    "write_bytes_per_kib": None,
+    "sources_sha256": "f971cdf7893320a20deaccd0e718a97a9e9560972ef06b158323c96c05f0ad9f",
+    "workload": {"windows": 32, "frontier_batch": 64},
+    "fetch_kib": 51254.6,
+    "write_kib": 416.7,
+    "fetch_bytes_per_kib": 1073741824 / 524305.0,
+    "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
                   "paper_2209_13168_amd/csrc/ecmd_api.hip")
@@ -150,12 +151,17 @@ def main():
     torch.cuda.synchronize()
     ctx.set_profiling(True)
     ctx.profile(reset=True)
+    # no Python garbage-collection pass inside the timed region (a full pass
+    # over torch's objects takes tens of milliseconds of host time)
+    gc.collect()
+    gc.disable()
     t0 = time.perf_counter()
     res = []
     for _ in range(args.steps):
         res.append(step())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    gc.enable()
     prof = ctx.profile(reset=True)
     ctx.set_profiling(False)
     sec = (t1 - t0) / args.steps

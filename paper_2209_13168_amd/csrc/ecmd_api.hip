@@ -123,9 +123,15 @@ struct Timers {
     ecmd_ctx* c;
     std::vector<Mark> marks;
     hipEvent_t pending = nullptr;
+    hipEvent_t last = nullptr;  // end event of the previous launch, if nothing was enqueued since
     explicit Timers(ecmd_ctx* ctx) : c(ctx) { c->ev_used = 0; }
     void begin() {
         if (!c->profiling) return;
+        if (last) {  // back-to-back launches share the boundary event
+            pending = last;
+            last = nullptr;
+            return;
+        }
         pending = pool_event(c);
         if (pending) (void)hipEventRecord(pending, c->stream);
     }
@@ -136,7 +142,10 @@ struct Timers {
         (void)hipEventRecord(b, c->stream);
         marks.push_back(Mark{pending, b, kind});
         pending = nullptr;
+        last = b;
     }
+    // other work is enqueued next: the following launch records its own start
+    void cut() { last = nullptr; }
     // after the stream has been synchronised
     void collect() {
         if (!c->profiling) return;
@@ -380,6 +389,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk);
     if (rc) return rc;
     tm.end(2);
+    tm.cut();
 
     Search sp;
     sp.d_lo = search->d_lo;
@@ -478,6 +488,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         } else {
             HIPCHK(c, step_pair(true));
             HIPCHK(c, step_pair(true));
+            tm.cut();
         }
         HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
