@@ -290,6 +290,8 @@ def main():
             "windows_per_s": round(nc / t_cpu, 4),
         }
     print(json.dumps(out), flush=True)
+    if net is not None:
+        net.close()
     ctx.close()
 
 

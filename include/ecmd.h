@@ -126,8 +126,11 @@ typedef struct {
 /* ------------------------------------------------------------ context */
 
 /* Create a context on HIP device `device`, ordering work on `hip_stream`
- * (a hipStream_t; NULL = the device's null stream).  The context owns all
- * device scratch; ecmd_ctx_destroy frees it. */
+ * (a hipStream_t; NULL = a blocking stream of default priority that the
+ * context creates and owns).  The context owns all device scratch;
+ * ecmd_ctx_destroy frees it, together with the device memory of every
+ * network still alive on it (those handles then accept only
+ * ecmd_cnn_destroy; every other call on them returns ECMD_EINVAL). */
 int ecmd_ctx_create(ecmd_ctx **out, int device, void *hip_stream);
 void ecmd_ctx_destroy(ecmd_ctx *ctx);
 /* Last error message of this context ("" if none). */
@@ -278,6 +281,7 @@ int ecmd_downsample(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
  * products accumulate in fp32.  Parameters are fp32 masters (Adam). */
 #define ECMD_CNN_NPARAM 23361
 int ecmd_cnn_create(ecmd_ctx *ctx, uint64_t seed, ecmd_cnn **out);
+/* Free a network (before or after its context is destroyed). */
 void ecmd_cnn_destroy(ecmd_cnn *cnn);
 /* Copy the fp32 parameter vector (ECMD_CNN_NPARAM values, host). */
 int ecmd_cnn_get_params(ecmd_cnn *cnn, float *host_params);

@@ -77,6 +77,7 @@ struct ecmd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    std::vector<ecmd_cnn*> nets;  // live networks created on this context
     int num_cu = 0;
     size_t max_lds = 0;
     size_t eval_lds = 0;   // LDS bytes of the last evaluation set-up (0 = none yet)
@@ -162,10 +163,16 @@ struct Timers {
 };
 
 struct ecmd_cnn {
-    ecmd_ctx* ctx = nullptr;
+    ecmd_ctx* ctx = nullptr;  // NULL once the context is destroyed
     DevBuf P, m, v, grad, pg, lossb, loss, out, imgs, labels, seeds;
     int step = 0;
 };
+
+static void cnn_release(ecmd_cnn* n) {
+    DevBuf* bufs[] = {&n->P, &n->m, &n->v, &n->grad, &n->pg, &n->lossb, &n->loss, &n->out, &n->imgs, &n->labels,
+                      &n->seeds};
+    for (DevBuf* b : bufs) b->release();
+}
 
 static int fail(ecmd_ctx* c, int code, const char* fmt, ...) {
     char buf[512];
@@ -629,6 +636,11 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
                       &c->front, &c->sel, &c->hyps, &c->act, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
                       &c->img, &c->keep, &c->counts, &c->misc};
     for (DevBuf* b : bufs) b->release();
+    // networks outlive their context only as empty handles
+    for (ecmd_cnn* n : c->nets) {
+        cnn_release(n);
+        n->ctx = nullptr;
+    }
     c->pinned.release();
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -1301,22 +1313,24 @@ int ecmd_cnn_create(ecmd_ctx* c, uint64_t seed, ecmd_cnn** out) {
     HIPCHK(c, hipMemcpy(n->P.p, p.data(), sizeof(float) * np, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(n->m.p, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(n->v.p, zero.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    c->nets.push_back(n);
     *out = n;
     return ECMD_OK;
 }
 
 void ecmd_cnn_destroy(ecmd_cnn* n) {
     if (!n) return;
-    (void)hipSetDevice(n->ctx->device);
-    (void)hipStreamSynchronize(n->ctx->stream);
-    DevBuf* bufs[] = {&n->P, &n->m, &n->v, &n->grad, &n->pg, &n->lossb, &n->loss, &n->out, &n->imgs, &n->labels,
-                      &n->seeds};
-    for (DevBuf* b : bufs) b->release();
+    if (ecmd_ctx* c = n->ctx) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        cnn_release(n);
+        c->nets.erase(std::remove(c->nets.begin(), c->nets.end(), n), c->nets.end());
+    }
     delete n;
 }
 
 int ecmd_cnn_get_params(ecmd_cnn* n, float* host_params) {
-    if (!n || !host_params) return ECMD_EINVAL;
+    if (!n || !n->ctx || !host_params) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipMemcpyAsync(host_params, n->P.p, sizeof(float) * cnn_nparam(), hipMemcpyDeviceToHost, c->stream));
@@ -1325,7 +1339,7 @@ int ecmd_cnn_get_params(ecmd_cnn* n, float* host_params) {
 }
 
 int ecmd_cnn_set_params(ecmd_cnn* n, const float* host_params) {
-    if (!n || !host_params) return ECMD_EINVAL;
+    if (!n || !n->ctx || !host_params) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;
     for (int k = 0; k < cnn_nparam(); ++k)
         if (!isfinite(host_params[k])) return fail(c, ECMD_EINVAL, "parameter %d is not finite", k);
@@ -1336,7 +1350,7 @@ int ecmd_cnn_set_params(ecmd_cnn* n, const float* host_params) {
 }
 
 int ecmd_cnn_forward(ecmd_cnn* n, const uint16_t* imgs, int32_t B, uint32_t flags, float* d_out) {
-    if (!n || !d_out) return ECMD_EINVAL;
+    if (!n || !n->ctx || !d_out) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;
     c->err.clear();
     int rc = cnn_run(n, imgs, nullptr, B, flags, 0);
@@ -1349,7 +1363,7 @@ int ecmd_cnn_forward(ecmd_cnn* n, const uint16_t* imgs, int32_t B, uint32_t flag
 
 int ecmd_cnn_grads(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32_t B, uint32_t flags,
                    float* grad_out, float* loss_out) {
-    if (!n || !grad_out || !loss_out) return ECMD_EINVAL;
+    if (!n || !n->ctx || !grad_out || !loss_out) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;
     c->err.clear();
     int rc = cnn_run(n, imgs, labels, B, flags, 1);
@@ -1362,7 +1376,7 @@ int ecmd_cnn_grads(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32
 
 int ecmd_cnn_train_step(ecmd_cnn* n, const uint16_t* imgs, const float* labels, int32_t B, float lr, uint32_t flags,
                         float* loss_out) {
-    if (!n) return ECMD_EINVAL;
+    if (!n || !n->ctx) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;
     c->err.clear();
     if (!(lr > 0.0f) || !isfinite(lr)) return fail(c, ECMD_EINVAL, "learning rate must be > 0");

@@ -84,3 +84,25 @@ def test_learned_seeding_keeps_the_certified_optimum(ctx, orc):
         assert r.status == 0 and (r.j_star, r.K) == (o.j_star, o.K)
         assert r.seeded == 1
     net.close()
+
+
+def test_network_outliving_its_context_is_rejected_not_used():
+    """Destroying a context releases its networks' device memory; the
+    orphaned handle then rejects every call except destroy."""
+    import ctypes as C
+
+    from paper_2209_13168_amd import ecmd
+
+    c = ecmd.Context(0)
+    net = ecmd.Cnn(c, seed=3)
+    h = net.h
+    c.close()
+    p = np.zeros(ecmd.CNN_NPARAM, np.float32)
+    assert ecmd.lib().ecmd_cnn_get_params(h, p.ctypes.data) == ecmd.EINVAL
+    assert ecmd.lib().ecmd_cnn_set_params(h, p.ctypes.data) == ecmd.EINVAL
+    out = np.zeros(1, np.float32)
+    img = np.zeros(4096, np.uint16)
+    assert ecmd.lib().ecmd_cnn_forward(h, img.ctypes.data, 1, 0, out.ctypes.data) == ecmd.EINVAL
+    assert ecmd.lib().ecmd_cnn_train_step(h, img.ctypes.data, out.ctypes.data, 1, C.c_float(1e-3), 0, None) == ecmd.EINVAL
+    net.close()  # frees the empty handle
+    assert net.h is None
