@@ -17,7 +17,9 @@
  *     upper-bound image H_bar (pixels crossed by the segment joining the
  *     warped endpoints, eq. (17)) and mu_low (segments fully in the image,
  *     eq. (20)), kept as K_bar = M*S_bar - N_low^2;
- *   - Algorithm 1 (best-first branch and bound) over a dyadic grid of d.
+ *   - Algorithm 1 (best-first branch and bound) over a dyadic grid of d;
+ *   - optionally, the event image kept per polarity (the *_pol functions),
+ *     with the contrast taken over both images together.
  *
  * Readings where the paper is silent (fixed so that results are exactly
  * checkable):
@@ -480,6 +482,144 @@ int orc_bnb(const float *x, const float *y, const float *t_rel, int64_t n,
     res->d_hat = orc_grid_d(d_lo, d_hi, L, res->j_star);
     res->d_end = (double)res->d_hat / (1.0 - (double)res->d_hat * (double)tau);
     free(k.e); free(k.r); free(k.img);
+    return rc;
+}
+
+/* ------------------------------------------------ polarity-aware contrast */
+
+/* The event image of eq. (13) kept per polarity (the paper notes after
+ * eq. (14) that polarity can be accommodated): H_-(u) counts the events with
+ * p <= 0 and H_+(u) those with p > 0.  The contrast of eq. (14) is then the
+ * variance over all 2M cells (u, polarity), kept as K = 2M*S - N^2 with S
+ * and N summed over both images.  Each image gets the upper bound of
+ * eqs. (15)-(20) unchanged: the bound image is H_bar_- next to H_bar_+ and
+ * N_low sums over both. */
+typedef struct {
+    ev32_t *e[2]; /* [0]: p <= 0, [1]: p > 0 */
+    int64_t n[2];
+} split32_t;
+
+static void split_free(split32_t *s)
+{
+    free(s->e[0]);
+    free(s->e[1]);
+}
+
+static int split_pol(const float *x, const float *y, const float *t_rel, const int8_t *pol,
+                     int64_t n, float tau, float cx, float cy, split32_t *s)
+{
+    memset(s, 0, sizeof(*s));
+    for (int l = 0; l < 2; ++l) {
+        int64_t m = 0;
+        for (int64_t i = 0; i < n; ++i) m += ((pol[i] > 0) == l);
+        size_t bytes = (size_t)(m > 0 ? m : 1) * sizeof(float);
+        float *bx = (float *)malloc(bytes), *by = (float *)malloc(bytes), *bt = (float *)malloc(bytes);
+        if (!bx || !by || !bt) { free(bx); free(by); free(bt); split_free(s); return ORC_ENOMEM; }
+        m = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if ((pol[i] > 0) != l) continue;
+            bx[m] = x[i]; by[m] = y[i]; bt[m] = t_rel[i];
+            ++m;
+        }
+        s->e[l] = prep32(bx, by, bt, m, tau, cx, cy);
+        s->n[l] = m;
+        free(bx); free(by); free(bt);
+        if (!s->e[l]) { split_free(s); return ORC_ENOMEM; }
+    }
+    return ORC_OK;
+}
+
+/* Point value with polarity: (S, N) over both images; img_out (nullable)
+ * receives H_- in its first W*H cells and H_+ in the next W*H. */
+int orc_point_pol(const float *x, const float *y, const float *t_rel, const int8_t *pol, int64_t n,
+                  int W, int H, float cx, float cy, float tau, float d,
+                  uint64_t *S, int64_t *N, uint32_t *img_out)
+{
+    int64_t M = (int64_t)W * H;
+    split32_t s;
+    if (split_pol(x, y, t_rel, pol, n, tau, cx, cy, &s)) return ORC_ENOMEM;
+    uint32_t *img = img_out ? img_out : (uint32_t *)malloc((size_t)(2 * M) * sizeof(uint32_t));
+    if (!img) { split_free(&s); return ORC_ENOMEM; }
+    float r = orc_rate(d, tau);
+    point_image32(s.e[0], s.n[0], W, H, r, img);
+    point_image32(s.e[1], s.n[1], W, H, r, img + M);
+    image_moments(img, 2 * M, S, N);
+    split_free(&s);
+    if (!img_out) free(img);
+    return ORC_OK;
+}
+
+/* Interval value with polarity: (S_bar, N_low) over both bound images. */
+int orc_bound_pol(const float *x, const float *y, const float *t_rel, const int8_t *pol, int64_t n,
+                  int W, int H, float cx, float cy, float tau, float d_a, float d_b,
+                  uint64_t *S_bar, int64_t *N_low, uint32_t *img_out)
+{
+    int64_t M = (int64_t)W * H, dummy;
+    if (!(d_a <= d_b)) return ORC_EINVAL;
+    split32_t s;
+    if (split_pol(x, y, t_rel, pol, n, tau, cx, cy, &s)) return ORC_ENOMEM;
+    uint32_t *img = img_out ? img_out : (uint32_t *)malloc((size_t)(2 * M) * sizeof(uint32_t));
+    if (!img) { split_free(&s); return ORC_ENOMEM; }
+    float ra = orc_rate(d_a, tau), rb = orc_rate(d_b, tau);
+    *N_low = bound_image32(s.e[0], s.n[0], W, H, ra, rb, img)
+           + bound_image32(s.e[1], s.n[1], W, H, ra, rb, img + M);
+    image_moments(img, 2 * M, S_bar, &dummy);
+    split_free(&s);
+    if (!img_out) free(img);
+    return ORC_OK;
+}
+
+typedef struct {
+    split32_t s;
+    int W, H;
+    int64_t M; /* W*H: cells per image */
+    float *r;
+    uint32_t *img; /* 2M cells */
+} ctxpol_t;
+
+static i128 ptpol(void *c, uint32_t j)
+{
+    ctxpol_t *k = (ctxpol_t *)c;
+    uint64_t S;
+    int64_t N;
+    point_image32(k->s.e[0], k->s.n[0], k->W, k->H, k->r[j], k->img);
+    point_image32(k->s.e[1], k->s.n[1], k->W, k->H, k->r[j], k->img + k->M);
+    image_moments(k->img, 2 * k->M, &S, &N);
+    return key_of(2 * k->M, S, N);
+}
+
+static i128 bdpol(void *c, uint32_t ja, uint32_t jb)
+{
+    ctxpol_t *k = (ctxpol_t *)c;
+    uint64_t S;
+    int64_t N;
+    int64_t n_low = bound_image32(k->s.e[0], k->s.n[0], k->W, k->H, k->r[ja], k->r[jb], k->img)
+                  + bound_image32(k->s.e[1], k->s.n[1], k->W, k->H, k->r[ja], k->r[jb], k->img + k->M);
+    image_moments(k->img, 2 * k->M, &S, &N);
+    return key_of(2 * k->M, S, n_low);
+}
+
+/* Canonical branch and bound (Algorithm 1) on the polarity-aware contrast. */
+int orc_bnb_pol(const float *x, const float *y, const float *t_rel, const int8_t *pol, int64_t n,
+                int W, int H, float cx, float cy, float tau,
+                float d_lo, float d_hi, float eps, double gamma, int64_t max_nodes,
+                orc_result_t *res)
+{
+    int rc = validate(n, W, H, tau, d_lo, d_hi, eps);
+    if (rc) { res->status = rc; return rc; }
+    int L = orc_depth(d_lo, d_hi, eps);
+    ctxpol_t k;
+    memset(&k, 0, sizeof k);
+    k.W = W; k.H = H; k.M = (int64_t)W * H;
+    if (split_pol(x, y, t_rel, pol, n, tau, cx, cy, &k.s)) { res->status = ORC_ENOMEM; return ORC_ENOMEM; }
+    k.r = (float *)malloc(((size_t)1 << L) * sizeof(float) + sizeof(float));
+    k.img = (uint32_t *)malloc((size_t)(2 * k.M) * sizeof(uint32_t));
+    if (!k.r || !k.img) { split_free(&k.s); free(k.r); free(k.img); res->status = ORC_ENOMEM; return ORC_ENOMEM; }
+    for (int64_t j = 0; j <= ((int64_t)1 << L); ++j) k.r[j] = orc_rate(orc_grid_d(d_lo, d_hi, L, j), tau);
+    rc = bnb_run(&k, ptpol, bdpol, L, 2 * k.M, gamma, max_nodes, res);
+    res->d_hat = orc_grid_d(d_lo, d_hi, L, res->j_star);
+    res->d_end = (double)res->d_hat / (1.0 - (double)res->d_hat * (double)tau);
+    split_free(&k.s); free(k.r); free(k.img);
     return rc;
 }
 

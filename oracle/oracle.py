@@ -67,6 +67,7 @@ _i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 _u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
 _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 _u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
+_i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
 
 
 def _bind(path: str):
@@ -96,6 +97,15 @@ def _bind(path: str):
     L.orc_dense.restype = C.c_int
     L.orc_point64.argtypes = ev + [C.c_double, C.POINTER(C.c_uint64), C.POINTER(C.c_int64)]
     L.orc_point64.restype = C.c_int
+    evp = [_f32p, _f32p, _f32p, _i8p, C.c_int64, C.c_int, C.c_int, C.c_float, C.c_float, C.c_float]
+    L.orc_point_pol.argtypes = evp + [C.c_float, C.POINTER(C.c_uint64), C.POINTER(C.c_int64), C.c_void_p]
+    L.orc_point_pol.restype = C.c_int
+    L.orc_bound_pol.argtypes = evp + [C.c_float, C.c_float, C.POINTER(C.c_uint64), C.POINTER(C.c_int64),
+                                      C.c_void_p]
+    L.orc_bound_pol.restype = C.c_int
+    L.orc_bnb_pol.argtypes = evp + [C.c_float, C.c_float, C.c_float, C.c_double, C.c_int64,
+                                    C.POINTER(OrcResult)]
+    L.orc_bnb_pol.restype = C.c_int
     L.orc_select.argtypes = [_f64p, C.c_int64, C.c_double, C.c_double, _i64p, _f32p]
     L.orc_select.restype = C.c_int64
     L.orc_downsample.argtypes = [_f32p, _f32p, C.c_int64, C.c_int, C.c_int, C.c_int, _u16p]
@@ -137,19 +147,25 @@ def _f32(a):
 
 class Events:
     """A window's events in the oracle's terms: positions, offsets from the
-    window start, the window length tau, sensor size and FOE."""
+    window start, the window length tau, sensor size and FOE, and optionally
+    the polarities (int8, > 0 positive) for the polarity-aware contrast."""
 
-    def __init__(self, x, y, t_rel, tau, W, H, foe):
+    def __init__(self, x, y, t_rel, tau, W, H, foe, p=None):
         self.x, self.y, self.t = _f32(x), _f32(y), _f32(t_rel)
         self.tau = float(np.float32(tau))
         self.W, self.H = int(W), int(H)
         self.cx, self.cy = float(np.float32(foe[0])), float(np.float32(foe[1]))
         self.n = int(self.x.shape[0])
+        self.p = None if p is None else np.ascontiguousarray(p, dtype=np.int8)
 
     @classmethod
-    def of_window(cls, w):
+    def of_window(cls, w, polarity: bool = False):
         s = w.spec
-        return cls(w.x, w.y, w.t_rel, s.tau, s.width, s.height, s.foe)
+        return cls(w.x, w.y, w.t_rel, s.tau, s.width, s.height, s.foe, w.p if polarity else None)
+
+    def _evp(self):
+        assert self.p is not None, "no polarities"
+        return (self.x, self.y, self.t, self.p, self.n, self.W, self.H, self.cx, self.cy, self.tau)
 
     @property
     def M(self) -> int:
@@ -254,3 +270,30 @@ def downsample(x, y, W: int, H: int, G: int = 64) -> np.ndarray:
     rc = lib().orc_downsample(_f32(x), _f32(y), int(np.asarray(x).shape[0]), W, H, G, out)
     assert rc == OK
     return out.reshape(G, G)
+
+
+# ------------------------------------------------- polarity-aware contrast
+
+def point_pol(ev: Events, d: float, want_image: bool = False):
+    """(S, N) over the two polarity images; the key uses 2M cells."""
+    S, N = C.c_uint64(), C.c_int64()
+    img = np.zeros(2 * ev.M, np.uint32) if want_image else None
+    rc = lib().orc_point_pol(*ev._evp(), d, C.byref(S), C.byref(N), img.ctypes.data if want_image else None)
+    assert rc == OK, rc
+    return (S.value, N.value, img) if want_image else (S.value, N.value)
+
+
+def bound_pol(ev: Events, d_a: float, d_b: float, want_image: bool = False):
+    S, N = C.c_uint64(), C.c_int64()
+    img = np.zeros(2 * ev.M, np.uint32) if want_image else None
+    rc = lib().orc_bound_pol(*ev._evp(), d_a, d_b, C.byref(S), C.byref(N),
+                             img.ctypes.data if want_image else None)
+    assert rc == OK, rc
+    return (S.value, N.value, img) if want_image else (S.value, N.value)
+
+
+def bnb_pol(ev: Events, d_lo: float, d_hi: float, eps: float, gamma: float = 0.0,
+            max_nodes: int = 0) -> BnbResult:
+    r = OrcResult()
+    lib().orc_bnb_pol(*ev._evp(), d_lo, d_hi, eps, gamma, max_nodes, C.byref(r))
+    return _res(r)

@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 from tests import test_oracle_pins as P
+from tests import test_oracle_polarity as PP
 
 MUTANTS = {
     # transposed pixel index (x and y swapped in the flat index)
@@ -30,6 +31,28 @@ MUTANTS = {
     "tie_prefers_larger_j": [("(Kc == K_inc && jc < j_inc)", "(Kc == K_inc && jc > j_inc)")],
     # children of 4-wide nodes never split
     "split_off_by_one": [("if (nd.jb - nd.ja >= 4) {", "if (nd.jb - nd.ja > 4) {")],
+}
+
+# planted mistakes in the polarity-aware statement, caught by its own pins
+POL_MUTANTS = {
+    # the key counts the cells of one image only
+    "pol_key_uses_M": [("return key_of(2 * k->M, S, N);", "return key_of(k->M, S, N);"),
+                       ("return key_of(2 * k->M, S, n_low);", "return key_of(k->M, S, n_low);"),
+                       ("rc = bnb_run(&k, ptpol, bdpol, L, 2 * k.M,", "rc = bnb_run(&k, ptpol, bdpol, L, k.M,")],
+    # both polarities binned into the same image
+    "pol_same_image": [("point_image32(s.e[1], s.n[1], W, H, r, img + M);",
+                        "point_image32(s.e[1], s.n[1], W, H, r, img);"),
+                       ("point_image32(k->s.e[1], k->s.n[1], k->W, k->H, k->r[j], k->img + k->M);",
+                        "point_image32(k->s.e[1], k->s.n[1], k->W, k->H, k->r[j], k->img);")],
+    # zero polarity counted as positive (split on >= 0)
+    "pol_split_sign": [("for (int64_t i = 0; i < n; ++i) m += ((pol[i] > 0) == l);",
+                        "for (int64_t i = 0; i < n; ++i) m += ((pol[i] >= 0) == l);"),
+                       ("if ((pol[i] > 0) != l) continue;", "if ((pol[i] >= 0) != l) continue;")],
+    # N_low of the second image dropped from the bound
+    "pol_bound_drops_nlow": [("int64_t n_low = bound_image32(k->s.e[0], k->s.n[0], k->W, k->H, k->r[ja], k->r[jb], k->img)\n"
+                              "                  + bound_image32(",
+                              "int64_t n_low = bound_image32(k->s.e[0], k->s.n[0], k->W, k->H, k->r[ja], k->r[jb], k->img);\n"
+                              "    (void)bound_image32(")],
 }
 
 PINS = [
@@ -68,3 +91,33 @@ def test_pins_catch_planted_mistake(orc, tmp_path, name):
                 break
     assert caught, f"no pin fails with the planted mistake {name}"
     assert os.path.exists(orc.LIB)
+
+
+POL_PINS = [
+    lambda o: PP.test_point_pol_is_bincount_over_two_images(o, "c1", None),
+    lambda o: PP.test_doubled_window_closed_form(o),
+    lambda o: PP.test_bound_pol_dominates_points(o),
+    lambda o: [PP.test_bnb_pol_equals_brute_force_tiny(o, k) for k in range(8)],
+    lambda o: PP.test_polarity_flip_and_single_polarity(o),
+]
+
+
+@pytest.mark.parametrize("name", sorted(POL_MUTANTS))
+def test_polarity_pins_catch_planted_mistake(orc, tmp_path, name):
+    src = open(orc.SRC).read()
+    for old, new in POL_MUTANTS[name]:
+        assert old in src, (name, old)
+        src = src.replace(old, new)
+    c = tmp_path / "mutant.c"
+    c.write_text(src)
+    so = str(tmp_path / "libmutant.so")
+    subprocess.run(["cc", *orc.CFLAGS, str(c), "-o", so, "-lm"], check=True)
+    caught = []
+    with orc.using(so):
+        for pin in POL_PINS:
+            try:
+                pin(orc)
+            except AssertionError:
+                caught.append(pin)
+                break
+    assert caught, f"no polarity pin fails with the planted mistake {name}"
