@@ -64,12 +64,19 @@ typedef struct {
 } ecmd_sensor;
 
 /* Events of a stream, structure of arrays.  t is absolute time in seconds
- * (sorted is not required).  Polarity is not used (Sec. 4.2). */
+ * (sorted is not required).  p (nullable, one byte per event, same memory
+ * kind as x) selects the polarity-aware contrast: NULL gives the event image
+ * of eq. (13), which ignores polarity; otherwise the events with p > 0 and
+ * those with p <= 0 form two images and the contrast of eq. (14) is the
+ * variance over all 2*W*H cells of both (the paper notes after eq. (14)
+ * that polarity can be accommodated); keys and contrasts then use
+ * M = 2*W*H.  Both +1/-1 and 1/0 encodings work. */
 typedef struct {
     const float *x;
     const float *y;
     const double *t;
     int64_t n;
+    const int8_t *p;
 } ecmd_events;
 
 /* Window [t0, t1] (closed): the batch of Sec. 3.3, tau = float(t1 - t0). */
@@ -204,6 +211,19 @@ int ecmd_estimate_divergence_batched(ecmd_ctx *ctx, const ecmd_sensor *sensor,
                                      const ecmd_search *search, uint32_t flags,
                                      const float *d_seeds, ecmd_result *out);
 
+/* The batched call on the polarity-aware contrast (see ecmd_events):
+ * polarity (non-NULL, one byte per event, indexed like x) splits every
+ * window's events into two event images; K and contrast use M = 2*W*H.
+ * The sensor may have at most 32 tiles (64 segments), a limit reached only
+ * by sensors far above 1280x720. */
+int ecmd_estimate_divergence_batched_polarity(ecmd_ctx *ctx, const ecmd_sensor *sensor,
+                                              const float *x, const float *y,
+                                              const float *t_rel, const int8_t *polarity,
+                                              const int64_t *offsets, const float *tau,
+                                              int32_t B, const ecmd_search *search,
+                                              uint32_t flags, const float *d_seeds,
+                                              ecmd_result *out);
+
 /* Stream estimation (Sec. 4.4): the events of [t_start, t_start + K tau)
  * are cut into K consecutive windows [t_start + k tau, t_start + (k+1) tau)
  * (half-open, fp64), each estimated as in the batched call (one launch
@@ -222,18 +242,24 @@ int ecmd_probe_pixels(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
                       float d, uint32_t flags, int32_t *pix_out);
 
 /* Point values (S_k, N_k) of m divergences d[k] (eqs. (13)-(14)); when
- * img_out is non-null it receives the m event images H (m*W*H uint32). */
+ * img_out is non-null it receives the m event images H (m*W*H uint32).
+ * polarity (nullable) as in ecmd_estimate_divergence_batched_polarity: S
+ * and N then cover both images and img_out holds 2*W*H cells per
+ * hypothesis (the p <= 0 image first). */
 int ecmd_probe_point(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
-                     const float *y, const float *t_rel, int64_t n, float tau,
+                     const float *y, const float *t_rel, const int8_t *polarity,
+                     int64_t n, float tau,
                      const float *d, int32_t m, uint32_t flags, uint64_t *S,
                      int64_t *N, uint32_t *img_out);
 
 /* Interval values (S_bar_k, N_low_k) of m intervals [d_a[k], d_b[k]]
  * (eqs. (17)-(20)); img_out (nullable) receives the m upper-bound images.
  * The search range [d_lo, d_hi] bounds every interval (it sets the event
- * binning); pass the range the intervals come from. */
+ * binning); pass the range the intervals come from.  polarity (nullable) as
+ * in ecmd_probe_point. */
 int ecmd_probe_bound(ecmd_ctx *ctx, const ecmd_sensor *sensor, const float *x,
-                     const float *y, const float *t_rel, int64_t n, float tau,
+                     const float *y, const float *t_rel, const int8_t *polarity,
+                     int64_t n, float tau,
                      float d_lo, float d_hi, const float *d_a, const float *d_b,
                      int32_t m, uint32_t flags, uint64_t *S_bar, int64_t *N_low,
                      uint32_t *img_out);

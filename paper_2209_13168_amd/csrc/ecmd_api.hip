@@ -83,7 +83,7 @@ struct ecmd_ctx {
     size_t eval_lds = 0;   // LDS bytes of the last evaluation set-up (0 = none yet)
     int eval_nb = 0;       // evaluation workgroups for that size
     // staging of host inputs
-    DevBuf sx, sy, st, soff, stau, sseed;
+    DevBuf sx, sy, st, soff, stau, sseed, spol;
     // prep
     DevBuf wp, blk, cnt_own, cnt_guest, seg_off, seg_own, cursor, ev, err_flag;
     // search
@@ -211,7 +211,9 @@ static int grid_depth(float d_lo, float d_hi, float eps) {
 // Tile plan: column and row cuts at the FOE lines when the FOE is an
 // integer point strictly inside the sensor (no event crosses them), then
 // each band split evenly until every tile fits the LDS budget.
-static bool plan_geometry(int W, int H, float cx, float cy, int max_px, Geometry& g) {
+// npol = 1, or 2 for the polarity-aware contrast (one tiled image per
+// polarity); segments = tiles x npol stay within kMaxTiles.
+static bool plan_geometry(int W, int H, float cx, float cy, int max_px, int npol, Geometry& g) {
     memset(&g, 0, sizeof g);
     g.W = W;
     g.H = H;
@@ -242,7 +244,7 @@ static bool plan_geometry(int W, int H, float cx, float cy, int max_px, Geometry
         for (int ky = 1; ky <= 32; ++ky) {
             std::vector<int> c = split(bx, kx), r = split(by, ky);
             int ntx = (int)c.size() - 1, nty = (int)r.size() - 1;
-            if (ntx * nty > kMaxTiles) continue;
+            if (ntx * nty * npol > kMaxTiles) continue;
             if ((long long)max_band(c) * max_band(r) > max_px) continue;
             // fewest tiles, then the squarest
             int score = ntx * nty * 1000 + std::abs(max_band(c) - max_band(r)) % 1000;
@@ -256,7 +258,8 @@ static bool plan_geometry(int W, int H, float cx, float cy, int max_px, Geometry
     if (best < 0) return false;
     g.ntx = (int)bc.size() - 1;
     g.nty = (int)br.size() - 1;
-    g.T = g.ntx * g.nty;
+    g.nsp = g.ntx * g.nty;
+    g.T = g.nsp * npol;
     for (int i = 0; i <= g.ntx; ++i) g.colcut[i] = bc[i];
     for (int i = 0; i <= g.nty; ++i) g.rowcut[i] = br[i];
     g.max_tile_px = max_band(bc) * max_band(br);
@@ -290,6 +293,7 @@ static int check_search(ecmd_ctx* c, const ecmd_search* s, int* L) {
 struct Inputs {
     const float *x = nullptr, *y = nullptr, *t = nullptr, *seeds = nullptr, *tau = nullptr;
     const long long* off = nullptr;
+    const signed char* pol = nullptr;  // polarities (device), or NULL: one event image
 };
 
 static int stage(ecmd_ctx* c, DevBuf& buf, const void* src, size_t bytes, uint32_t flags,
@@ -337,7 +341,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
     HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
     // count + scan (scatter needs the total to size the event store)
-    HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
+    HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
                           c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>()));
     HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
@@ -350,7 +354,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     if (errf)
         return fail(c, ECMD_EINVAL, "an event has a non-finite coordinate or t_rel outside [0, tau]");
     HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)std::max(total, 1ll)));
-    HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
+    HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
                           c->ev.as<float4>(), nullptr));
     *nblk_out = nblk;
@@ -385,11 +389,12 @@ static hipError_t eval_setup(ecmd_ctx* c, size_t lds, int* nb) {
 static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, int B,
                       const ecmd_search* search, int L, ecmd_result* out) {
     const int W = sensor->width, H = sensor->height;
-    const long long M = (long long)W * H;
+    const int npol = in.pol ? 2 : 1;
+    const long long M = (long long)W * H * npol;  // cells of the event image(s): the key is M*S - N^2
     Geometry g;
     const int budget = c->tune.tile_px > 0 ? std::min(c->tune.tile_px, tile_budget(c)) : tile_budget(c);
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, g))
-        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles);
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, npol, g))
+        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
     Timers tm(c);
     int nblk = 0;
     tm.begin();
@@ -537,7 +542,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
 }
 
 static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y,
-                        const float* t_rel, const int64_t* offsets, const float* tau, int32_t B,
+                        const float* t_rel, const int8_t* pol, const int64_t* offsets, const float* tau, int32_t B,
                         const ecmd_search* search, uint32_t flags, const float* d_seeds, ecmd_result* out) {
     if (!c) return ECMD_EINVAL;
     c->err.clear();
@@ -587,6 +592,10 @@ static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, 
     in.off = (const long long*)p;
     if ((rc = stage(c, c->stau, tau, sizeof(float) * B, flags, &p))) return rc;
     in.tau = (const float*)p;
+    if (pol) {
+        if ((rc = stage(c, c->spol, pol, (size_t)n_total, flags, &p))) return rc;
+        in.pol = (const signed char*)p;
+    }
     if (d_seeds) {
         if ((rc = stage(c, c->sseed, d_seeds, sizeof(float) * B, flags, &p))) return rc;
         in.seeds = (const float*)p;
@@ -631,7 +640,7 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    DevBuf* bufs[] = {&c->sx, &c->sy, &c->st, &c->soff, &c->stau, &c->sseed, &c->wp, &c->blk, &c->cnt_own,
+    DevBuf* bufs[] = {&c->sx, &c->sy, &c->st, &c->soff, &c->stau, &c->sseed, &c->spol, &c->wp, &c->blk, &c->cnt_own,
                       &c->cnt_guest, &c->seg_off, &c->seg_own, &c->cursor, &c->ev, &c->err_flag, &c->state,
                       &c->front, &c->sel, &c->hyps, &c->act, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
                       &c->img, &c->keep, &c->counts, &c->misc};
@@ -692,7 +701,8 @@ int ecmd_autotune(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const 
                 double ms = 1e300;
                 for (int rep = 0; rep < 3; ++rep) {
                     auto t0 = std::chrono::steady_clock::now();
-                    int rc = batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, &s, flags, nullptr, out.data());
+                    int rc = batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, &s, flags, nullptr,
+                                          out.data());
                     auto t1 = std::chrono::steady_clock::now();
                     if (rc < 0 && rc != ECMD_EBUDGET && rc != ECMD_EFRONTIER) {
                         c->tune = saved;
@@ -732,7 +742,17 @@ int ecmd_estimate_divergence_batched(ecmd_ctx* c, const ecmd_sensor* sensor, con
                                      const float* t_rel, const int64_t* offsets, const float* tau, int32_t B,
                                      const ecmd_search* search, uint32_t flags, const float* d_seeds,
                                      ecmd_result* out) {
-    return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, d_seeds, out);
+    return batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, search, flags, d_seeds, out);
+}
+
+int ecmd_estimate_divergence_batched_polarity(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x,
+                                              const float* y, const float* t_rel, const int8_t* polarity,
+                                              const int64_t* offsets, const float* tau, int32_t B,
+                                              const ecmd_search* search, uint32_t flags, const float* d_seeds,
+                                              ecmd_result* out) {
+    if (!c) return ECMD_EINVAL;
+    if (!polarity && B > 0) return fail(c, ECMD_EINVAL, "polarity is NULL");
+    return batched_impl(c, sensor, x, y, t_rel, polarity, offsets, tau, B, search, flags, d_seeds, out);
 }
 
 int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_events* events,
@@ -752,6 +772,8 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
     float* dx;
     float* dy;
     float* dt;
+    const bool has_pol = events->p != nullptr;
+    if (has_pol) HIPCHK(c, c->spol.ensure((size_t)std::max(n, 1ll)));
     if (flags & ECMD_DEVICE_PTR) {
         HIPCHK(c, c->sx.ensure(sizeof(float) * std::max(n, 1ll)));
         HIPCHK(c, c->sy.ensure(sizeof(float) * std::max(n, 1ll)));
@@ -761,8 +783,10 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
         HIPCHK(c, c->misc.ensure(sizeof(long long)));
         HIPCHK(c, c->err_flag.ensure(sizeof(int)));
         HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
-        HIPCHK(c, launch_select(c->stream, events->x, events->y, events->t, n, window.t0, window.t1, c->sx.as<float>(),
-                                c->sy.as<float>(), c->st.as<float>(), c->keep.as<int>(), c->misc.as<long long>()));
+        HIPCHK(c, launch_select(c->stream, events->x, events->y, events->t, (const signed char*)events->p, n,
+                                window.t0, window.t1, c->sx.as<float>(), c->sy.as<float>(), c->st.as<float>(),
+                                has_pol ? c->spol.as<signed char>() : nullptr, c->keep.as<int>(),
+                                c->misc.as<long long>()));
         HIPCHK(c, c->pinned.ensure(64));
         HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->misc.p, sizeof(long long), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -772,6 +796,7 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
         dt = c->st.as<float>();
     } else {
         std::vector<float> hx, hy, ht;
+        std::vector<signed char> hp;
         hx.reserve(n);
         for (long long i = 0; i < n; ++i) {
             double t = events->t[i];
@@ -779,6 +804,7 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
                 hx.push_back(events->x[i]);
                 hy.push_back(events->y[i]);
                 ht.push_back((float)(t - window.t0));
+                if (has_pol) hp.push_back((signed char)events->p[i]);
             }
         }
         m = (long long)hx.size();
@@ -789,6 +815,7 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
             HIPCHK(c, hipMemcpyAsync(c->sx.p, hx.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->sy.p, hy.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(c->st.p, ht.data(), sizeof(float) * m, hipMemcpyHostToDevice, c->stream));
+            if (has_pol) HIPCHK(c, hipMemcpyAsync(c->spol.p, hp.data(), (size_t)m, hipMemcpyHostToDevice, c->stream));
         }
         HIPCHK(c, hipStreamSynchronize(c->stream));  // host vectors die at scope end
         dx = c->sx.as<float>();
@@ -816,6 +843,7 @@ int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_
         in.x = dx;
         in.y = dy;
         in.t = dt;
+        if (has_pol) in.pol = c->spol.as<signed char>();
         const void* p;
         if ((rc = stage(c, c->soff, off, sizeof off, 0, &p))) return rc;
         in.off = (const long long*)p;
@@ -858,7 +886,7 @@ int ecmd_probe_pixels(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
 
 // Evaluate m hypotheses (points if d_b == NULL) on one window.
 static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
-                      int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
+                      const int8_t* pol, int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
                       uint32_t flags, uint64_t* S, int64_t* N, uint32_t* img_out) {
     if (!c) return ECMD_EINVAL;
     c->err.clear();
@@ -871,10 +899,11 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
         return fail(c, ECMD_EINVAL, "probe range must satisfy 0 <= d_lo <= d_hi, d_hi * tau < 1");
     HIPCHK(c, hipSetDevice(c->device));
     const int W = sensor->width, H = sensor->height;
-    const long long M = (long long)W * H;
+    const int npol = pol ? 2 : 1;
+    const long long M = (long long)W * H * npol;  // image cells per hypothesis
     Geometry g;
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), g))
-        return fail(c, ECMD_EINVAL, "sensor needs more than %d tiles", kMaxTiles);
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), npol, g))
+        return fail(c, ECMD_EINVAL, "sensor needs more than %d tiles", kMaxTiles / npol);
     const int T = g.T;
     Inputs in;
     const void* p;
@@ -884,6 +913,10 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     in.y = (const float*)p;
     if ((rc = stage(c, c->st, t_rel, sizeof(float) * n, flags, &p))) return rc;
     in.t = (const float*)p;
+    if (pol) {
+        if ((rc = stage(c, c->spol, pol, (size_t)n, flags, &p))) return rc;
+        in.pol = (const signed char*)p;
+    }
     long long off[2] = {0, n};
     if ((rc = stage(c, c->soff, off, sizeof off, 0, &p))) return rc;
     in.off = (const long long*)p;
@@ -963,7 +996,7 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
 }
 
 int ecmd_probe_point(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
-                     int64_t n, float tau, const float* d, int32_t m, uint32_t flags, uint64_t* S, int64_t* N,
+                     const int8_t* polarity, int64_t n, float tau, const float* d, int32_t m, uint32_t flags, uint64_t* S, int64_t* N,
                      uint32_t* img_out) {
     if (!c) return ECMD_EINVAL;
     if (m < 0 || (m > 0 && !d)) return fail(c, ECMD_EINVAL, "bad probe arguments");
@@ -983,11 +1016,11 @@ int ecmd_probe_point(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, con
         hi = std::max(hi, v);
     }
     if (m == 0) lo = hi = 0.0f;
-    return probe_impl(c, sensor, x, y, t_rel, n, tau, lo, hi, d, nullptr, m, flags, S, N, img_out);
+    return probe_impl(c, sensor, x, y, t_rel, polarity, n, tau, lo, hi, d, nullptr, m, flags, S, N, img_out);
 }
 
 int ecmd_probe_bound(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const float* t_rel,
-                     int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
+                     const int8_t* polarity, int64_t n, float tau, float d_lo, float d_hi, const float* d_a, const float* d_b, int32_t m,
                      uint32_t flags, uint64_t* S_bar, int64_t* N_low, uint32_t* img_out) {
     if (!c) return ECMD_EINVAL;
     if (m > 0 && (!d_a || !d_b)) return fail(c, ECMD_EINVAL, "NULL interval ends");
@@ -1004,7 +1037,8 @@ int ecmd_probe_bound(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, con
     for (int k = 0; k < m; ++k)
         if (!(ha[k] >= d_lo && ha[k] <= hb[k] && hb[k] <= d_hi))
             return fail(c, ECMD_EINVAL, "interval %d not inside [d_lo, d_hi] or reversed", k);
-    return probe_impl(c, sensor, x, y, t_rel, n, tau, d_lo, d_hi, d_a, d_b, m, flags, S_bar, N_low, img_out);
+    return probe_impl(c, sensor, x, y, t_rel, polarity, n, tau, d_lo, d_hi, d_a, d_b, m, flags, S_bar, N_low,
+                      img_out);
 }
 
 int ecmd_downsample(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const float* y, const int64_t* offsets,
@@ -1186,6 +1220,12 @@ int ecmd_estimate_stream(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_even
     for (int k = 0; k <= K; ++k) rel[k] = off[k] - o0;
     std::vector<float> taus(K, (float)tau);
     const float *dx = events->x + o0, *dy = events->y + o0;
+    const signed char* dp = events->p ? (const signed char*)events->p + o0 : nullptr;
+    if (events->p && !(flags & ECMD_DEVICE_PTR)) {
+        HIPCHK(c, c->spol.ensure((size_t)std::max(m, 1ll)));
+        if (m) HIPCHK(c, hipMemcpyAsync(c->spol.p, events->p + o0, (size_t)m, hipMemcpyHostToDevice, c->stream));
+        dp = c->spol.as<signed char>();
+    }
     if (!(flags & ECMD_DEVICE_PTR)) {
         HIPCHK(c, c->img.ensure(sizeof(float) * 2 * std::max(m, 1ll)));
         float* sxy = c->img.as<float>();
@@ -1209,6 +1249,7 @@ int ecmd_estimate_stream(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_even
     in.x = dx;
     in.y = dy;
     in.t = trel;
+    in.pol = dp;
     const void* p;
     if ((rc = stage(c, c->soff, rel.data(), sizeof(long long) * (K + 1), 0, &p))) return rc;
     in.off = (const long long*)p;
@@ -1421,11 +1462,12 @@ int ecmd_estimate_divergence_learned(ecmd_ctx* c, ecmd_cnn* n, const ecmd_sensor
     HIPCHK(c, launch_seed_from_pred(c->stream, n->out.as<float>(), B, search->d_lo, search->d_hi,
                                     n->seeds.as<float>()));
     if (flags & ECMD_DEVICE_PTR)
-        return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, n->seeds.as<float>(), out);
+        return batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, search, flags, n->seeds.as<float>(),
+                            out);
     std::vector<float> hs(B);
     HIPCHK(c, hipMemcpyAsync(hs.data(), n->seeds.p, sizeof(float) * B, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return batched_impl(c, sensor, x, y, t_rel, offsets, tau, B, search, flags, hs.data(), out);
+    return batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, search, flags, hs.data(), out);
 }
 
 }  // extern "C"

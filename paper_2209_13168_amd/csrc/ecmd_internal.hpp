@@ -54,7 +54,8 @@ struct Sel {
 struct Geometry {
     int W, H;
     float cx, cy;
-    int T;                        // number of tiles
+    int T;                        // number of event segments per window: nsp spatial tiles x 1 or 2 polarity images
+    int nsp;                      // spatial tiles (ntx * nty); segment t covers tile t % nsp of image t / nsp
     int ntx, nty;                 // tile grid
     int colcut[kMaxTiles + 1];    // column band edges (ntx + 1)
     int rowcut[kMaxTiles + 1];    // row band edges (nty + 1)
@@ -131,7 +132,7 @@ size_t prep_counters(int B, int T);
 // phase 0: count events per (window, tile, owned/guest, walk class) and scan
 // into segments; phase 1: scatter the events into their segments.
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
-                       const float* t_rel, const long long* offsets, const WinParam* wp, int B,
+                       const float* t_rel, const signed char* pol, const long long* offsets, const WinParam* wp, int B,
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
                        unsigned long long* cursor, float4* ev, int* err_flag);
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
@@ -156,10 +157,11 @@ hipError_t eval_set_lds(size_t bytes);
 // LDS bytes of the evaluation kernel for tiles of up to max_tile_px pixels.
 size_t eval_lds_bytes(int max_tile_px);
 hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes);
-// Events with t in [t0, t1], compacted in order, t_rel = float(t - t0).
-hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, long long n,
-                         double t0, double t1, float* xo, float* yo, float* to, int* blk_cnt,
-                         long long* total);
+// Events with t in [t0, t1], compacted in order, t_rel = float(t - t0);
+// their polarities too when p is not NULL.
+hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, const signed char* p,
+                         long long n, double t0, double t1, float* xo, float* yo, float* to, signed char* po,
+                         int* blk_cnt, long long* total);
 
 // preprocessing (ecmd_preproc.hip)
 hipError_t launch_compact(hipStream_t s, const float* x, const float* y, const float* t, const long long* offsets,

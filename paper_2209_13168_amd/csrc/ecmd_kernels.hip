@@ -142,6 +142,12 @@ __device__ __forceinline__ int walk_class(float ax, float ay, float kscale) {
 // counter of (tile, owned 0 / guest 1, walk class) inside a window
 __device__ __forceinline__ int ctr_of(int t, int og, int b) { return (t * 2 + og) * kNB + b; }
 
+// First segment of event i's image: the polarity-aware contrast keeps one
+// event image per polarity (p > 0: the second), each tiled alike.
+__device__ __forceinline__ int seg_base(const Geometry& g, const signed char* pol, long long i) {
+    return (pol && pol[i] > 0) ? g.nsp : 0;
+}
+
 constexpr int kPrepThreads = 256;
 constexpr int kCtr = kMaxTiles * 2 * kNB;
 
@@ -169,7 +175,7 @@ __device__ __forceinline__ PrepEv prep_event(const Geometry& g, const WinParam& 
 
 __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     Geometry g, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ t_rel,
-    const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
+    const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, int* __restrict__ cnt, int* __restrict__ err_flag) {
     __shared__ int s_cnt[kCtr];
     const int nc = g.T * 2 * kNB;
@@ -184,9 +190,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.valid) atomicOr(err_flag, 1);
         if (!e.ok) continue;
+        const int sb = seg_base(g, pol, i);
         for (int ty = e.ty0; ty <= e.ty1; ++ty)
             for (int tx = e.tx0; tx <= e.tx1; ++tx)
-                atomicAdd(&s_cnt[ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
+                atomicAdd(&s_cnt[ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nc; k += blockDim.x)
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_prep_scan(int B, int T, const int* __r
 
 __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     Geometry g, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ t_rel,
-    const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
+    const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, unsigned long long* __restrict__ cursor,
     float4* __restrict__ ev) {
     __shared__ int s_cnt[kCtr];
@@ -248,9 +255,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.ok) continue;
+        const int sb = seg_base(g, pol, i);
         for (int ty = e.ty0; ty <= e.ty1; ++ty)
             for (int tx = e.tx0; tx <= e.tx1; ++tx)
-                atomicAdd(&s_cnt[ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
+                atomicAdd(&s_cnt[ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nc; k += blockDim.x) {
@@ -263,9 +271,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.ok) continue;
         const float4 v = make_float4(e.x, e.y, e.ax, e.ay);
+        const int sb = seg_base(g, pol, i);
         for (int ty = e.ty0; ty <= e.ty1; ++ty)
             for (int tx = e.tx0; tx <= e.tx1; ++tx) {
-                const int k = ctr_of(ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls);
+                const int k = ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls);
                 const int r = atomicAdd(&s_cnt[k], 1);
                 ev[s_base[k] + (unsigned long long)r] = v;
             }
@@ -275,12 +284,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
 size_t prep_counters(int B, int T) { return (size_t)B * T * 2 * kNB; }
 
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
-                       const float* t_rel, const long long* offsets, const WinParam* wp, int B,
+                       const float* t_rel, const signed char* pol, const long long* offsets, const WinParam* wp, int B,
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
                        unsigned long long* cursor, float4* ev, int* err_flag) {
     if (phase == 0) {
         if (nblk > 0) {
-            k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk, cnt,
+            k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cnt,
                                                        err_flag);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
@@ -289,7 +298,8 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
         return hipGetLastError();
     }
     if (nblk > 0) {
-        k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, offsets, wp, B, blk_start, chunk, cursor, ev);
+        k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cursor,
+                                                     ev);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -403,7 +413,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         if (it < 0) break;
         const Item item = items[it];
         const int w = item.w, t = item.t;
-        const int tx = t % g.ntx, ty = t / g.ntx;
+        const int ts = t % g.nsp;  // spatial tile of the segment
+        const int tx = ts % g.ntx, ty = ts / g.ntx;
         const int x0 = g.colcut[tx], y0 = g.rowcut[ty];
         const unsigned tw = (unsigned)(g.colcut[tx + 1] - x0), th = (unsigned)(g.rowcut[ty + 1] - y0);
         const int npx = (int)(tw * th);
@@ -510,11 +521,12 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             pt.pad = 0;
             part[(long long)wh * g.T + t] = pt;
         }
-        if (img_out) {
+        if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
             const long long M = (long long)g.W * g.H;
+            unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
             for (int k = tid; k < npx; k += kEvalThreads) {
                 int lx = k % (int)tw, ly = k / (int)tw;
-                img_out[(long long)wh * M + (long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
+                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
             }
         }
         __syncthreads();  // the tile is cleared again for the next hypothesis
@@ -1029,10 +1041,11 @@ __global__ __launch_bounds__(1024) void k_select_scan(int nb, int* __restrict__ 
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_select_write(const float* __restrict__ x, const float* __restrict__ y,
-                                                              const double* __restrict__ t, long long n, double t0,
-                                                              double t1, const int* __restrict__ blk_off,
+                                                              const double* __restrict__ t,
+                                                              const signed char* __restrict__ p, long long n,
+                                                              double t0, double t1, const int* __restrict__ blk_off,
                                                               float* __restrict__ xo, float* __restrict__ yo,
-                                                              float* __restrict__ to) {
+                                                              float* __restrict__ to, signed char* __restrict__ po) {
     __shared__ int s[kSelThreads];
     long long i = (long long)blockIdx.x * kSelThreads + threadIdx.x;
     int keep = (i < n && t[i] >= t0 && t[i] <= t1) ? 1 : 0;
@@ -1049,11 +1062,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select_write(const float* __res
         xo[k] = x[i];
         yo[k] = y[i];
         to[k] = (float)(t[i] - t0);
+        if (p) po[k] = p[i];
     }
 }
 
-hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, long long n, double t0,
-                         double t1, float* xo, float* yo, float* to, int* blk_cnt, long long* total) {
+hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, const signed char* p,
+                         long long n, double t0, double t1, float* xo, float* yo, float* to, signed char* po,
+                         int* blk_cnt, long long* total) {
     const int nb = (int)((n + kSelThreads - 1) / kSelThreads);
     if (nb > 0) {
         k_select_count<<<nb, kSelThreads, 0, s>>>(t, n, t0, t1, blk_cnt);
@@ -1063,7 +1078,7 @@ hipError_t launch_select(hipStream_t s, const float* x, const float* y, const do
     k_select_scan<<<1, 1024, 0, s>>>(nb, blk_cnt, total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nb == 0) return e;
-    k_select_write<<<nb, kSelThreads, 0, s>>>(x, y, t, n, t0, t1, blk_cnt, xo, yo, to);
+    k_select_write<<<nb, kSelThreads, 0, s>>>(x, y, t, p, n, t0, t1, blk_cnt, xo, yo, to, po);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ class Sensor(C.Structure):
 
 
 class EventsS(C.Structure):
-    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("t", C.c_void_p), ("n", C.c_int64)]
+    _fields_ = [("x", C.c_void_p), ("y", C.c_void_p), ("t", C.c_void_p), ("n", C.c_int64), ("p", C.c_void_p)]
 
 
 class WindowS(C.Structure):
@@ -111,10 +111,12 @@ def _load():
                                       C.POINTER(SearchS), u32, vp, C.POINTER(ResultS)], C.c_int),
         "ecmd_estimate_divergence_batched": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32,
                                               C.POINTER(SearchS), u32, vp, C.POINTER(ResultS)], C.c_int),
+        "ecmd_estimate_divergence_batched_polarity": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, vp, i32,
+                                                       C.POINTER(SearchS), u32, vp, C.POINTER(ResultS)], C.c_int),
         "ecmd_probe_pixels": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, f32, u32, vp], C.c_int),
-        "ecmd_probe_point": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, vp, i32, u32, vp, vp, vp],
+        "ecmd_probe_point": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, i64, f32, vp, i32, u32, vp, vp, vp],
                              C.c_int),
-        "ecmd_probe_bound": ([vp, C.POINTER(Sensor), vp, vp, vp, i64, f32, f32, f32, vp, vp, i32, u32,
+        "ecmd_probe_bound": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, i64, f32, f32, f32, vp, vp, i32, u32,
                               vp, vp, vp], C.c_int),
         "ecmd_downsample": ([vp, C.POINTER(Sensor), vp, vp, vp, i32, u32, vp], C.c_int),
         "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
@@ -177,7 +179,7 @@ class _Args:
 
             tdt = {np.float32: torch.float32, np.float64: torch.float64, np.int64: torch.int64,
                    np.int32: torch.int32, np.uint64: torch.int64, np.uint32: torch.int32,
-                   np.uint16: torch.int16}[dtype]
+                   np.uint16: torch.int16, np.int8: torch.int8}[dtype]
             if a.dtype != tdt or not a.is_contiguous() or not a.is_cuda:
                 raise TypeError(f"expected a contiguous CUDA tensor of {tdt}, got {a.dtype} on {a.device}")
             if self.device is False:
@@ -305,10 +307,13 @@ class Context:
     # ---------------------------------------------------------- estimation
     def estimate(self, sensor: Sensor, x, y, t, t0: float, t1: float, d_lo: float, d_hi: float, eps: float,
                  gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0, frontier_capacity: int = 0,
-                 d_seed: Optional[float] = None) -> Result:
+                 d_seed: Optional[float] = None, polarity=None) -> Result:
+        """One window [t0, t1] of a stream; polarity (int8, optional) selects
+        the polarity-aware contrast."""
         a = _Args()
         n = int(x.shape[0])
-        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n)
+        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n,
+                     a.ptr(polarity, np.int8))
         sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
         seed = C.c_float(d_seed) if d_seed is not None else None
         out = ResultS()
@@ -319,7 +324,9 @@ class Context:
 
     def estimate_batched(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
                          eps: float, gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0,
-                         frontier_capacity: int = 0, d_seeds=None) -> list:
+                         frontier_capacity: int = 0, d_seeds=None, polarity=None) -> list:
+        """B windows in one call; polarity (int8 per event, optional) selects
+        the polarity-aware contrast."""
         a = _Args()
         B = int(tau.shape[0])
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
@@ -327,8 +334,13 @@ class Context:
         ps = a.ptr(d_seeds, np.float32) if d_seeds is not None else None
         sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
         out = (ResultS * max(B, 1))()
-        rc = lib().ecmd_estimate_divergence_batched(self.h, C.byref(sensor), px, py, pt, po, ptau, B, C.byref(sp),
-                                                    a.flags, ps, out)
+        if polarity is None:
+            rc = lib().ecmd_estimate_divergence_batched(self.h, C.byref(sensor), px, py, pt, po, ptau, B,
+                                                        C.byref(sp), a.flags, ps, out)
+        else:
+            pp = a.ptr(polarity, np.int8)
+            rc = lib().ecmd_estimate_divergence_batched_polarity(self.h, C.byref(sensor), px, py, pt, pp, po, ptau,
+                                                                 B, C.byref(sp), a.flags, ps, out)
         self._check(rc, allow=(EBUDGET, EFRONTIER))
         return [Result.of(out[i]) for i in range(B)]
 
@@ -344,31 +356,35 @@ class Context:
                                             a.flags, po))
         return out
 
-    def probe_point(self, sensor: Sensor, x, y, t_rel, tau: float, d, want_image: bool = False):
+    def probe_point(self, sensor: Sensor, x, y, t_rel, tau: float, d, want_image: bool = False, polarity=None):
         a = _Args()
         n = int(x.shape[0])
         m = int(d.shape[0])
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        pp = a.ptr(polarity, np.int8)
         pd = a.ptr(d, np.float32)
         S = _empty_like(x, m, np.uint64)
         N = _empty_like(x, m, np.int64)
-        img = _empty_like(x, m * sensor.width * sensor.height, np.uint32) if want_image else None
-        self._check(lib().ecmd_probe_point(self.h, C.byref(sensor), px, py, pt, n, float(tau), pd, m, a.flags,
+        cells = sensor.width * sensor.height * (1 if polarity is None else 2)
+        img = _empty_like(x, m * cells, np.uint32) if want_image else None
+        self._check(lib().ecmd_probe_point(self.h, C.byref(sensor), px, py, pt, pp, n, float(tau), pd, m, a.flags,
                                            a.ptr(S, np.uint64), a.ptr(N, np.int64),
                                            a.ptr(img, np.uint32) if want_image else None))
         return (S, N, img) if want_image else (S, N)
 
     def probe_bound(self, sensor: Sensor, x, y, t_rel, tau: float, d_lo: float, d_hi: float, d_a, d_b,
-                    want_image: bool = False):
+                    want_image: bool = False, polarity=None):
         a = _Args()
         n = int(x.shape[0])
         m = int(d_a.shape[0])
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
+        pp = a.ptr(polarity, np.int8)
         pa, pb = a.ptr(d_a, np.float32), a.ptr(d_b, np.float32)
         S = _empty_like(x, m, np.uint64)
         N = _empty_like(x, m, np.int64)
-        img = _empty_like(x, m * sensor.width * sensor.height, np.uint32) if want_image else None
-        self._check(lib().ecmd_probe_bound(self.h, C.byref(sensor), px, py, pt, n, float(tau), float(d_lo),
+        cells = sensor.width * sensor.height * (1 if polarity is None else 2)
+        img = _empty_like(x, m * cells, np.uint32) if want_image else None
+        self._check(lib().ecmd_probe_bound(self.h, C.byref(sensor), px, py, pt, pp, n, float(tau), float(d_lo),
                                            float(d_hi), pa, pb, m, a.flags, a.ptr(S, np.uint64),
                                            a.ptr(N, np.int64), a.ptr(img, np.uint32) if want_image else None))
         return (S, N, img) if want_image else (S, N)
@@ -389,11 +405,12 @@ class Context:
         return [Result.of(out[i]) for i in range(B)]
 
     def estimate_stream(self, sensor: Sensor, x, y, t, t_start: float, tau: float, K: int, d_lo: float,
-                        d_hi: float, eps: float, **kw) -> list:
+                        d_hi: float, eps: float, polarity=None, **kw) -> list:
         """K consecutive windows of length tau from t_start (Sec. 4.4)."""
         a = _Args()
         n = int(x.shape[0])
-        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n)
+        ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n,
+                     a.ptr(polarity, np.int8))
         sp = _search(d_lo, d_hi, eps, **kw)
         out = (ResultS * max(K, 1))()
         rc = lib().ecmd_estimate_stream(self.h, C.byref(sensor), C.byref(ev), float(t_start), float(tau), int(K),

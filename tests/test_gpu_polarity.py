@@ -1,0 +1,177 @@
+"""Parity of the polarity-aware contrast on the HIP path (through the C ABI)
+with the oracle's statement: per-polarity event images, key 2M*S - N^2.
+
+Values (S, N, images, optima) match bit for bit; at full size a property
+that holds at any size is checked: a window doubled with opposite
+polarities has four times the polarity-blind key and the same search."""
+
+import numpy as np
+import pytest
+
+from synth import config_windows, pack_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    assert torch.cuda.is_available()
+    c = ecmd.Context(0)
+    yield c
+    c.close()
+
+
+def _sensor(spec, foe=None):
+    from paper_2209_13168_amd import ecmd
+
+    return ecmd.sensor(spec.width, spec.height, foe or spec.foe)
+
+
+def _pol_events(orc, w, foe=None):
+    s = w.spec
+    return orc.Events(w.x, w.y, w.t_rel, s.tau, s.width, s.height, foe or s.foe, w.p)
+
+
+CASES = [
+    ("c1", {}, None),
+    ("c2", {"n_events": 30_000}, None),
+    ("c2", {"n_events": 8_000}, (101.3, 57.85)),
+    ("c3", {"n_events": 40_000}, None),
+    ("c5", {"n_events": 50_000}, None),
+]
+
+
+@pytest.mark.parametrize("cfg,kw,foe", CASES)
+def test_point_and_bound_values_bit_exact(ctx, orc, cfg, kw, foe):
+    w = config_windows(cfg, [7], **kw)[0]
+    s = w.spec
+    ev = _pol_events(orc, w, foe)
+    M2 = 2 * s.width * s.height
+    rng = np.random.default_rng(11)
+    ds = np.concatenate([rng.uniform(s.d_lo, s.d_hi * 0.99, 5), [0.0, s.d_true]]).astype(np.float32)
+    S, N, img = ctx.probe_point(_sensor(s, foe), w.x, w.y, w.t_rel, s.tau, ds, want_image=True, polarity=w.p)
+    for k, d in enumerate(ds):
+        So, No, Ho = orc.point_pol(ev, float(d), want_image=True)
+        assert (int(S[k]), int(N[k])) == (So, No), (k, d)
+        assert np.array_equal(img[k * M2:(k + 1) * M2], Ho)
+    L = orc.depth(s.d_lo, s.d_hi, s.eps)
+    da, db = [], []
+    for depth in (0, 2, 5, 9, L - 1):
+        size = 1 << (L - depth)
+        ja = int(rng.integers(0, 1 << depth)) * size
+        da.append(orc.grid_d(s.d_lo, s.d_hi, L, ja))
+        db.append(orc.grid_d(s.d_lo, s.d_hi, L, ja + size))
+    da, db = np.array(da, np.float32), np.array(db, np.float32)
+    Sb, Nl, imgb = ctx.probe_bound(_sensor(s, foe), w.x, w.y, w.t_rel, s.tau, s.d_lo, s.d_hi, da, db,
+                                   want_image=True, polarity=w.p)
+    for k in range(da.size):
+        So, No, Ho = orc.bound_pol(ev, float(da[k]), float(db[k]), want_image=True)
+        assert (int(Sb[k]), int(Nl[k])) == (So, No), (k, da[k], db[k])
+        assert np.array_equal(imgb[k * M2:(k + 1) * M2], Ho)
+
+
+def _same(r, o):
+    assert r.status == 0, r
+    assert (r.j_star, r.K) == (o.j_star, o.K), (r, o)
+
+
+def test_bnb_batched_matches_oracle(ctx, orc):
+    """Mixed batch: 128x128 windows and 346x260 windows of several sizes."""
+    ws = config_windows("c2", range(3), n_events=20_000) + [config_windows("c2", [3])[0]]
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    p = np.concatenate([w.p for w in ws])
+    res = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, polarity=p)
+    for w, r in zip(ws, res):
+        _same(r, orc.bnb_pol(_pol_events(orc, w), s.d_lo, s.d_hi, s.eps))
+    for k in range(3):
+        w = config_windows("c1", [k])[0]
+        s1 = w.spec
+        x, y, t, off, tau = pack_batch([w])
+        r = ctx.estimate_batched(_sensor(s1), x, y, t, off, tau, s1.d_lo, s1.d_hi, s1.eps, polarity=w.p)[0]
+        _same(r, orc.bnb_pol(_pol_events(orc, w), s1.d_lo, s1.d_hi, s1.eps))
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_bnb_tiny_windows(ctx, orc, k):
+    w = config_windows("tiny", [k])[0]
+    s = w.spec
+    x, y, t, off, tau = pack_batch([w])
+    r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, polarity=w.p)[0]
+    _same(r, orc.bnb_pol(_pol_events(orc, w), s.d_lo, s.d_hi, s.eps))
+
+
+def test_single_window_and_stream_entry_points(ctx, orc):
+    """Absolute-time entry points carry polarity through window selection
+    (host and device arrays)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    w = config_windows("c1", [4])[0]
+    s = w.spec
+    o = orc.bnb_pol(_pol_events(orc, w), s.d_lo, s.d_hi, s.eps)
+    r = ctx.estimate(_sensor(s), w.x, w.y, w.t, s.t0, w.t1, s.d_lo, s.d_hi, s.eps, polarity=w.p)
+    _same(r, o)
+    T = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    rd = ctx.estimate(_sensor(s), T(w.x), T(w.y), T(w.t), s.t0, w.t1, s.d_lo, s.d_hi, s.eps, polarity=T(w.p))
+    _same(rd, o)
+
+    ws = config_windows("c2", range(3), n_events=12_000)
+    s = ws[0].spec
+    tau = float(np.float32(s.tau))
+    t0 = 20.0
+    t = np.concatenate([t0 + k * tau + v.t_rel.astype(np.float64) for k, v in enumerate(ws)])
+    x = np.concatenate([v.x for v in ws])
+    y = np.concatenate([v.y for v in ws])
+    p = np.concatenate([v.p for v in ws])
+    host = ctx.estimate_stream(_sensor(s), x, y, t, t0, tau, len(ws), s.d_lo, s.d_hi, 1e-4, polarity=p)
+    devr = ctx.estimate_stream(_sensor(s), T(x), T(y), T(t), t0, tau, len(ws), s.d_lo, s.d_hi, 1e-4,
+                               polarity=T(p))
+    for k in range(len(ws)):
+        lo, hi = t0 + k * tau, t0 + (k + 1) * tau
+        sel = (t >= lo) & (t < hi)
+        ev = orc.Events(x[sel], y[sel], (t[sel] - lo).astype(np.float32), tau, s.width, s.height, s.foe, p[sel])
+        o = orc.bnb_pol(ev, s.d_lo, s.d_hi, 1e-4)
+        _same(host[k], o)
+        _same(devr[k], o)
+
+
+def test_doubled_full_size_windows_scale_the_blind_search(ctx):
+    """Full-size 640x480 windows (up to 1M events each, doubled): every key of
+    the doubled window with opposite polarities is 4x the blind key, so the
+    certified optimum is the same grid point with 4x the key and the search
+    takes the same decisions (same node and evaluation counts)."""
+    import torch
+
+    from paper_2209_13168_amd.learned import windows_chunks
+
+    dev = torch.device("cuda:0")
+    idx = [56, 9, 11]  # the smallest and two large windows of the 64-window batch
+    for x, y, t, offs, tau, _ in windows_chunks(idx, cfg="c3", chunk=3):
+        pass
+    from synth.ventral import config_specs
+
+    s = config_specs("c3", 0)
+    B = len(idx)
+    blind = ctx.estimate_batched(_sensor(s), *(torch.from_numpy(a).to(dev) for a in (x, y, t, offs, tau)),
+                                 s.d_lo, s.d_hi, s.eps)
+    xs, ys, ts, ps = [], [], [], []
+    offs2 = np.zeros(B + 1, np.int64)
+    for b in range(B):
+        a, e = offs[b], offs[b + 1]
+        xs += [x[a:e], x[a:e]]
+        ys += [y[a:e], y[a:e]]
+        ts += [t[a:e], t[a:e]]
+        ps += [np.ones(e - a, np.int8), -np.ones(e - a, np.int8)]
+        offs2[b + 1] = offs2[b] + 2 * (e - a)
+    args = [torch.from_numpy(np.concatenate(v)).to(dev) for v in (xs, ys, ts)]
+    dbl = ctx.estimate_batched(_sensor(s), *args, torch.from_numpy(offs2).to(dev), torch.from_numpy(tau).to(dev),
+                               s.d_lo, s.d_hi, s.eps, polarity=torch.from_numpy(np.concatenate(ps)).to(dev))
+    for r, q in zip(blind, dbl):
+        assert r.status == 0 and q.status == 0
+        assert (q.j_star, q.K) == (r.j_star, 4 * r.K)
+        assert (q.nodes_expanded, q.point_evals, q.bound_evals) == (r.nodes_expanded, r.point_evals, r.bound_evals)
