@@ -190,6 +190,18 @@ def main():
         assert [(r.j_star, r.K) for r in rl] == [(r.j_star, r.K) for r in last]
         nodes_learned = float(np.mean([r.nodes_expanded for r in rl]))
 
+    # the same batch handed over in host memory (the library stages it to
+    # the device: PCIe-inclusive rate)
+    ctx.estimate_batched(sensor, x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, **kw)
+    torch.cuda.synchronize()
+    a0 = time.perf_counter()
+    reps = max(3, args.steps // 4)
+    for _ in range(reps):
+        rh = ctx.estimate_batched(sensor, x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, **kw)
+    torch.cuda.synchronize()
+    host_ws = B * reps / (time.perf_counter() - a0)
+    assert [(r.j_star, r.K) for r in rh] == [(r.j_star, r.K) for r in last]
+
     # plain: one window per call, no batching
     P = min(args.plain_windows, B)
     plain_t = []
@@ -254,6 +266,7 @@ def main():
         "windows_per_s": {
             "batched": round(B / sec, 2),
             "batched_learned": round(learned_ws, 2) if learned_ws else None,
+            "batched_from_host_buffers": round(host_ws, 2),
             "plain_one_window_per_call": round(P / sum(plain_t), 2) if plain_t else None,
         },
         "search": {
