@@ -63,9 +63,25 @@ __device__ __forceinline__ int bitlen128(i128 v) {
     return 0;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// One step of a DPP wave reduction of a 64-bit value: add the value that
+// DPP control CTRL routes to this lane (rows outside ROWMASK add zero).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ unsigned long long dpp_add(unsigned long long v) {
+    const unsigned lo = __builtin_amdgcn_update_dpp(0u, (unsigned)v, CTRL, ROWMASK, 0xf, false);
+    const unsigned hi = __builtin_amdgcn_update_dpp(0u, (unsigned)(v >> 32), CTRL, ROWMASK, 0xf, false);
+    return v + (((unsigned long long)hi << 32) | lo);
+}
+
+// Sum over the 64 lanes of a wave in registers (no LDS): quad swaps, half-row
+// and row mirrors give every lane its row's sum; the two row broadcasts then
+// carry rows 0-2 into row 3.  The total is valid in lane 63 (all lanes active).
+__device__ __forceinline__ unsigned long long wave_total(unsigned long long v) {
+    v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
 }
 
@@ -358,11 +374,17 @@ __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned 
 }
 
 // LDS layout of k_eval: [tile: tw*th counters][spill: one word per thread]
-// [reduction scratch][work item].
+// (region rounded up to 16 bytes)[reduction scratch][work item].
 constexpr int kEvalWaves = kEvalThreads / 64;
 
+// Counter words of the LDS tile region (tile + one spill word per thread),
+// rounded up to whole 16-byte units so the clear can use 16-byte stores.
+__host__ __device__ __forceinline__ int eval_counter_words(int max_tile_px) {
+    return (max_tile_px + kEvalThreads + 3) & ~3;
+}
+
 size_t eval_lds_bytes(int max_tile_px) {
-    return (size_t)(max_tile_px + kEvalThreads) * 4 + 3 * kEvalWaves * 8 + 16;
+    return (size_t)eval_counter_words(max_tile_px) * 4 + 3 * kEvalWaves * 8 + 16;
 }
 
 // Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
@@ -375,11 +397,11 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const int* __restrict__ act,
     const Item* __restrict__ items, int qcap, Queue* __restrict__ q, Queue* __restrict__ q_reset,
     Part* __restrict__ part, int HS, unsigned* __restrict__ img_out) {
-    extern __shared__ unsigned smem[];
+    extern __shared__ __align__(16) unsigned smem[];
     const int tid = threadIdx.x;
     unsigned* const tile = smem;
     unsigned long long* const s_red =
-        reinterpret_cast<unsigned long long*>(smem + g.max_tile_px + kEvalThreads);
+        reinterpret_cast<unsigned long long*>(smem + eval_counter_words(g.max_tile_px));
     int* const s_item = reinterpret_cast<int*>(s_red + 3 * kEvalWaves);
     if (blockIdx.x == 0 && tid < kXcd && q_reset) {
         q_reset[tid].n_items = 0;
@@ -426,7 +448,11 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const int wh = w * HS + act[w * HS + item.r0 + gk];
         const Hyp hp = hyps[wh];
 
-        for (int i = tid; i < npx + kEvalThreads; i += kEvalThreads) tile[i] = 0u;
+        {  // clear the tile and the spill words, 16 bytes per store
+            uint4* const t4 = reinterpret_cast<uint4*>(tile);
+            const int n4 = (npx + kEvalThreads + 3) >> 2;
+            for (int i = tid; i < n4; i += kEvalThreads) t4[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
         __syncthreads();
 
         unsigned long long sumold = 0, nlow = 0;
@@ -497,11 +523,11 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         unsigned long long hits = (unsigned long long)(visits - m);
         unsigned long long sq = 2ull * sumold + hits;
         // block reduction of (S, hits, nlow)
-        sq = wave_sum(sq);
-        hits = wave_sum(hits);
-        nlow = wave_sum(nlow);
+        sq = wave_total(sq);
+        hits = wave_total(hits);
+        nlow = wave_total(nlow);
         const int wave = tid >> 6, lane = tid & 63;
-        if (lane == 0) {
+        if (lane == 63) {
             s_red[wave] = sq;
             s_red[kEvalWaves + wave] = hits;
             s_red[2 * kEvalWaves + wave] = nlow;
