@@ -415,10 +415,12 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     const int T = g.T;
-    // hypotheses per work item: enough items to fill the GPU, fewer set-ups
+    // hypotheses per work item: fewer set-ups, but still ~48 items per CU so
+    // that the launch does not end on a few long items (measured: 2 for 32
+    // windows of 346x260, 1 for 8 or fewer)
     {
         const long long work = (long long)B * sp.HS * T;
-        const long long slots = (long long)c->num_cu * 8;
+        const long long slots = (long long)c->num_cu * 48;
         sp.G = (int)std::max(1ll, std::min(8ll, work / std::max(slots, 1ll)));
         if (c->tune.group > 0) sp.G = std::min(c->tune.group, 64);
     }
