@@ -407,7 +407,6 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         q_reset[tid].n_items = 0;
         q_reset[tid].next = 0;
     }
-    const float Wf = (float)g.W, Hf = (float)g.H;
     const int home = blockIdx.x % kXcd;
     int qi = 0;  // queues tried so far, starting at this XCD's own (thread 0 only)
     int qn[kXcd];  // queue sizes, read once (thread 0 only)
@@ -499,22 +498,35 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
             WalkAcc acc{0ull, 0u, 0u};
-            unsigned i = tid;
-            float4 e = at(min(i, nseg - 1));
-            for (; i < nseg; i += kEvalThreads) {
-                const float4 en = at(min(i + kEvalThreads, nseg - 1));  // prefetch while walking
+            unsigned nlow32 = 0;
+            const auto one = [&](const float4& e, unsigned i) {
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
-                nlow += (i < nown) & inside(xa, ya, Wf, Hf) & inside(xb, yb, Wf, Hf);
                 const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
+                nlow32 += (unsigned)(i < nown) & (unsigned)(max((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
+                          (unsigned)(max((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
                 tile_add(tile, spill, x0, y0, tw, th, kxa, kya, acc);
                 if (kxa != kxb || kya != kyb)
                     walk_tile(tile, spill, x0, y0, tw, th, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
-                e = en;
+            };
+            unsigned i = tid;
+            if (i < nseg) {
+                float4 e0 = at(i), e1;
+                for (;;) {
+                    e1 = at(min(i + kEvalThreads, nseg - 1));
+                    one(e0, i);
+                    i += kEvalThreads;
+                    if (i >= nseg) break;
+                    e0 = at(min(i + kEvalThreads, nseg - 1));
+                    one(e1, i);
+                    i += kEvalThreads;
+                    if (i >= nseg) break;
+                }
             }
             sumold = acc.sumold + acc.pend;
             visits = acc.visits;
+            nlow = nlow32;
         }
         // Remove the spill word, whose m increments returned 0, 1, .., m-1;
         // then the sum of squares is sum(2*old + 1) over the in-tile increments.
