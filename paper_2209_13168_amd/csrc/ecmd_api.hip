@@ -353,7 +353,9 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     const int errf = *(int*)((char*)c->pinned.p + 8);
     if (errf)
         return fail(c, ECMD_EINVAL, "an event has a non-finite coordinate or t_rel outside [0, tau]");
-    HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)std::max(total, 1ll)));
+    // one stride of padding: the evaluation kernel prefetches up to
+    // kEvalThreads records past the end of a segment
+    HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)(total + kEvalThreads)));
     HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
                           c->ev.as<float4>(), nullptr));

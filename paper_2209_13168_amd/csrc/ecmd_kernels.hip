@@ -335,7 +335,7 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 struct WalkAcc {
     unsigned long long sumold;
     unsigned pend;
-    unsigned visits;
+    unsigned visits;  // walk increments (the start pixels are counted by the caller)
 };
 
 __device__ __forceinline__ void tile_add(unsigned* __restrict__ tile, unsigned spill, int x0, int y0, unsigned tw,
@@ -345,7 +345,6 @@ __device__ __forceinline__ void tile_add(unsigned* __restrict__ tile, unsigned s
     const unsigned old = atomicAdd(&tile[a], 1u);
     acc.sumold += acc.pend;
     acc.pend = old;
-    acc.visits += 1;
 }
 
 __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned spill, int x0, int y0,
@@ -366,10 +365,12 @@ __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned 
         if (dx && dy && !lo && !hi) {  // the ray passes near the corner: both side pixels
             tile_add(tile, spill, x0, y0, tw, th, kx + sx, ky, acc);
             tile_add(tile, spill, x0, y0, tw, th, kx, ky + sy, acc);
+            acc.visits += 2;
         }
         kx += (dx && (!dy || !hi)) ? sx : 0;
         ky += (dy && (!dx || !lo)) ? sy : 0;
         tile_add(tile, spill, x0, y0, tw, th, kx, ky, acc);
+        acc.visits += 1;
     } while (kx != kxb || ky != kyb);
 }
 
@@ -455,12 +456,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         __syncthreads();
 
         unsigned long long sumold = 0, nlow = 0;
-        unsigned visits = 0;
+        unsigned visits = 0;  // increments by this thread: one per event, plus walk steps
         // the segment's events, indexed from its start with 32-bit offsets
         // (byte offsets fit 32 bits: a segment holds fewer than 2^28 events)
         const char* __restrict__ sev = reinterpret_cast<const char*>(ev + beg);
         const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
         const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
+        visits = (unsigned)tid < nseg ? (nseg - 1u - (unsigned)tid) / kEvalThreads + 1u : 0u;
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
             // flight, loads first, then U increments without branches.
@@ -484,7 +486,6 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 for (int k = 0; k < U; ++k) old[k] = atomicAdd(&tile[a[k]], 1u);
 #pragma unroll
                 for (int k = 0; k < U; ++k) sumold += old[k];
-                visits += U;
             }
             for (; i < nseg; i += S) {
                 const float4 e = at(i);
@@ -492,7 +493,6 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 const unsigned ly = (unsigned)(cvt_flr(fmaf(e.w, r, e.y)) - y0);
                 const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
                 sumold += atomicAdd(&tile[a], 1u);
-                visits += 1;
             }
         } else {
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
@@ -514,18 +514,18 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             if (i < nseg) {
                 float4 e0 = at(i), e1;
                 for (;;) {
-                    e1 = at(min(i + kEvalThreads, nseg - 1));
+                    e1 = at(i + kEvalThreads);  // may read past the segment: the store is padded
                     one(e0, i);
                     i += kEvalThreads;
                     if (i >= nseg) break;
-                    e0 = at(min(i + kEvalThreads, nseg - 1));
+                    e0 = at(i + kEvalThreads);
                     one(e1, i);
                     i += kEvalThreads;
                     if (i >= nseg) break;
                 }
             }
             sumold = acc.sumold + acc.pend;
-            visits = acc.visits;
+            visits += acc.visits;
             nlow = nlow32;
         }
         // Remove the spill word, whose m increments returned 0, 1, .., m-1;
