@@ -179,6 +179,32 @@ typedef struct {
 int ecmd_ctx_set_tuning(ecmd_ctx *ctx, const ecmd_tuning *tuning);
 int ecmd_ctx_get_tuning(const ecmd_ctx *ctx, ecmd_tuning *out);
 
+/* Search plan, computed on the host without a device: the grid depth L of
+ * the dyadic grid (smallest L >= 1 with (d_hi - d_lo) 2^-L <= eps), and
+ * the image tiling the evaluation kernel uses — cuts at the FOE lines when
+ * the FOE is an integer point strictly inside the sensor (the warp of
+ * eq. (12) never moves an event across them), bands split evenly until each
+ * tile's counters fit the LDS.  lds_bytes = LDS per workgroup (0 = 160 KiB,
+ * gfx950); tile_px caps the tile size as ecmd_tuning.tile_px does;
+ * polarity != 0 plans the two images of the polarity-aware contrast. */
+typedef struct {
+    int32_t L;
+    int32_t segments;        /* event segments per window: tiles x images */
+    int32_t ntx, nty;        /* tile grid */
+    int32_t max_tile_px;     /* largest tile (pixels) */
+    int32_t tile_budget_px;  /* the size limit the plan met */
+    int32_t colcut[65];      /* column band edges, ntx + 1 used */
+    int32_t rowcut[65];      /* row band edges, nty + 1 used */
+} ecmd_plan_info;
+
+int ecmd_plan(const ecmd_sensor *sensor, const ecmd_search *search, int32_t polarity,
+              int64_t lds_bytes, int32_t tile_px, ecmd_plan_info *out);
+
+/* Grid point d_j = float(d_lo + (d_hi - d_lo) j 2^-L), computed in fp64
+ * (the candidates of the search are j = 1 .. 2^L - 1); NaN when L is
+ * outside 1..30 or j > 2^L.  Host only. */
+float ecmd_grid_point(float d_lo, float d_hi, uint32_t L, uint32_t j);
+
 /* Autotuner: times candidate tunings (frontier batch, tile size, graph
  * replay, hypotheses per item) on the given batch (arguments as ecmd_estimate_divergence_batched,
  * with search->frontier_batch ignored), keeps the fastest in the context and

@@ -364,11 +364,13 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
 }
 
 // Largest tile (pixels) whose evaluation workgroup fits the LDS.
-static int tile_budget(ecmd_ctx* c) {
-    int px = (int)(c->max_lds / 4) - kEvalThreads - 64;
-    while (px > 0 && eval_lds_bytes(px) > c->max_lds) --px;
+static int tile_budget_for(size_t max_lds) {
+    int px = (int)(max_lds / 4) - kEvalThreads - 64;
+    while (px > 0 && eval_lds_bytes(px) > max_lds) --px;
     return px;
 }
+
+static int tile_budget(ecmd_ctx* c) { return tile_budget_for(c->max_lds); }
 
 // Persistent workgroup count of the evaluation kernel for `lds` bytes of
 // LDS: as many as fit at once, at most 4 per CU.  The kernel's dynamic LDS
@@ -662,6 +664,38 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
 }
 
 const char* ecmd_last_error(const ecmd_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int ecmd_plan(const ecmd_sensor* sensor, const ecmd_search* search, int32_t polarity, int64_t lds_bytes,
+              int32_t tile_px, ecmd_plan_info* out) {
+    if (!sensor || !search || !out || lds_bytes < 0 || tile_px < 0) return ECMD_EINVAL;
+    if (sensor->width <= 0 || sensor->height <= 0 || sensor->width > 32768 || sensor->height > 32768)
+        return ECMD_EINVAL;
+    if (!isfinite(sensor->foe_x) || !isfinite(sensor->foe_y)) return ECMD_EINVAL;
+    if (!(search->eps > 0.0f) || !(search->d_lo >= 0.0f) || !(search->d_lo < search->d_hi)) return ECMD_EINVAL;
+    const int L = grid_depth(search->d_lo, search->d_hi, search->eps);
+    if (L < 1) return ECMD_EINVAL;
+    const int npol = polarity ? 2 : 1;
+    const int budget0 = tile_budget_for(lds_bytes ? (size_t)lds_bytes : (size_t)160 * 1024);
+    const int budget = tile_px > 0 ? std::min(tile_px, budget0) : budget0;
+    Geometry g;
+    if (!plan_geometry(sensor->width, sensor->height, sensor->foe_x, sensor->foe_y, budget, npol, g))
+        return ECMD_EINVAL;
+    memset(out, 0, sizeof *out);
+    out->L = L;
+    out->segments = g.T;
+    out->ntx = g.ntx;
+    out->nty = g.nty;
+    out->max_tile_px = g.max_tile_px;
+    out->tile_budget_px = budget;
+    for (int i = 0; i <= g.ntx; ++i) out->colcut[i] = g.colcut[i];
+    for (int i = 0; i <= g.nty; ++i) out->rowcut[i] = g.rowcut[i];
+    return ECMD_OK;
+}
+
+float ecmd_grid_point(float d_lo, float d_hi, uint32_t L, uint32_t j) {
+    if (L < 1 || L > 30 || j > (1u << L)) return NAN;
+    return host_grid_d(d_lo, d_hi, (int)L, j);
+}
 
 int ecmd_ctx_set_tuning(ecmd_ctx* c, const ecmd_tuning* t) {
     if (!c || !t) return ECMD_EINVAL;

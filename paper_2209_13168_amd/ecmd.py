@@ -59,6 +59,12 @@ class ResultS(C.Structure):
                 ("steps", C.c_int32), ("seeded", C.c_int32)]
 
 
+class PlanInfo(C.Structure):
+    _fields_ = [("L", C.c_int32), ("segments", C.c_int32), ("ntx", C.c_int32), ("nty", C.c_int32),
+                ("max_tile_px", C.c_int32), ("tile_budget_px", C.c_int32), ("colcut", C.c_int32 * 65),
+                ("rowcut", C.c_int32 * 65)]
+
+
 class TuningS(C.Structure):
     _fields_ = [("frontier_batch", C.c_int32), ("tile_px", C.c_int32), ("graph", C.c_int32),
                 ("group", C.c_int32)]
@@ -120,6 +126,8 @@ def _load():
                               vp, vp, vp], C.c_int),
         "ecmd_downsample": ([vp, C.POINTER(Sensor), vp, vp, vp, i32, u32, vp], C.c_int),
         "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
+        "ecmd_plan": ([C.POINTER(Sensor), C.POINTER(SearchS), i32, i64, i32, C.POINTER(PlanInfo)], C.c_int),
+        "ecmd_grid_point": ([f32, f32, u32, u32], f32),
         "ecmd_ctx_set_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_ctx_get_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_autotune": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32, C.POINTER(SearchS), u32,
@@ -202,6 +210,23 @@ class _Args:
 def _search(d_lo, d_hi, eps, gamma=0.0, max_nodes=0, frontier_batch=0, frontier_capacity=0) -> SearchS:
     return SearchS(float(d_lo), float(d_hi), float(eps), 0.0, float(gamma), int(max_nodes),
                    int(frontier_batch), int(frontier_capacity))
+
+
+def plan(sensor: Sensor, d_lo: float, d_hi: float, eps: float, polarity: bool = False, lds_bytes: int = 0,
+         tile_px: int = 0) -> dict:
+    """Grid depth and image tiling of a search (host only, no device)."""
+    out = PlanInfo()
+    rc = lib().ecmd_plan(C.byref(sensor), C.byref(_search(d_lo, d_hi, eps)), 1 if polarity else 0, int(lds_bytes),
+                         int(tile_px), C.byref(out))
+    if rc != OK:
+        raise EcmdError(rc, "invalid plan arguments")
+    return {"L": out.L, "segments": out.segments, "ntx": out.ntx, "nty": out.nty, "max_tile_px": out.max_tile_px,
+            "tile_budget_px": out.tile_budget_px, "colcut": list(out.colcut[:out.ntx + 1]),
+            "rowcut": list(out.rowcut[:out.nty + 1])}
+
+
+def grid_point(d_lo: float, d_hi: float, L: int, j: int) -> float:
+    return float(lib().ecmd_grid_point(float(d_lo), float(d_hi), int(L), int(j)))
 
 
 class Context:
