@@ -30,6 +30,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "event-hypothesis evals/sec; BnB windows/sec (plain vs batched+learned) at fixed eps"
+WORKLOADS = {
+    "c2": "{B} windows of the 346x260 config per step: 100k events/0.25 s window, D in [0,1.5], eps 1e-5 (L=18), "
+          "batched certified BnB",
+    "c3": "{B} windows of the 640x480 config per step: 50k-1M events (log-uniform) per 0.25 s window, D drifting "
+          "0.1 to 0.6, D in [0,1.5], eps 1e-5 (L=18), batched certified BnB",
+    "c5": "{B} windows of the 1280x720 config per step: 100k-5M events (log-uniform) per 0.25 s window plus hot "
+          "pixels, D in [0,2], eps 1e-5 (L=18), batched certified BnB",
+}
 
 # Algorithmic VALU lane-operations of the fp32 statement per unit of work:
 OPS_POINT = 8      # per event and point hypothesis: 2 fma, 2 floor, 2 range tests, 1 index, 1 accumulate
@@ -49,7 +57,7 @@ EVENT_RECORD_BYTES = 16
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
     "sources_sha256": "6a4a1e447c0dd5fc60cd8c24ae4e68f9628d870d78a0b74d79261248058f1807",
-    "workload": {"windows": 32, "frontier_batch": 64},
+    "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
     "fetch_kib": 28114.0,
     "write_kib": 457.8,
     "fetch_bytes_per_kib": 1073741824 / 524304.7,
@@ -80,11 +88,15 @@ def traffic_per_launch(workload: dict):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--windows", type=int, default=32, help="windows per step")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20; 3 for c3 and c5)")
+    ap.add_argument("--warmup", type=int, default=None, help="warm-up steps (default 3; 1 for c3 and c5)")
+    ap.add_argument("--config", choices=["c2", "c3", "c5"], default="c2",
+                    help="c2: 32 windows of 346x260 (the default workload); c3: the 64-window 640x480 batch; "
+                         "c5: the 256-window 1280x720 batch with hot pixels")
+    ap.add_argument("--windows", type=int, default=32, help="windows per step (c2)")
     ap.add_argument("--frontier-batch", type=int, default=0)
-    ap.add_argument("--plain-windows", type=int, default=8, help="windows timed one call each")
+    ap.add_argument("--plain-windows", type=int, default=None,
+                    help="windows timed one call each (default 8 for c2, all windows of the batch for c3 and c5)")
     ap.add_argument("--cpu-windows", type=int, default=8, help="oracle sample size (windows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
@@ -123,10 +135,31 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_launch": a.numel() * 4, "launches": 3}))
         return
-    B = args.windows
-    wins = config_windows("c2", range(B))
-    s = wins[0].spec
-    x, y, t, off, tau = pack_batch(wins)
+    big = args.config != "c2"
+    if args.steps is None:
+        args.steps = 3 if big else 20
+    if args.warmup is None:
+        args.warmup = 1 if big else 3
+    if args.plain_windows is None:
+        args.plain_windows = 10**9 if big else 8
+    if big:
+        from paper_2209_13168_amd.learned import windows_chunks
+        from synth.ventral import config_specs
+
+        B = {"c3": 64, "c5": 256}[args.config]
+        parts = list(windows_chunks(list(range(B)), cfg=args.config, chunk=32))
+        x, y, t = (np.concatenate([p[k] for p in parts]) for k in range(3))
+        tau = np.concatenate([p[4] for p in parts])
+        off = np.zeros(B + 1, np.int64)
+        off[1:] = np.cumsum(np.concatenate([np.diff(p[3]) for p in parts]))
+        s = config_specs(args.config, 0)
+        win = lambda k: config_windows(args.config, [k])[0]  # noqa: E731
+    else:
+        B = args.windows
+        wins = config_windows("c2", range(B))
+        s = wins[0].spec
+        x, y, t, off, tau = pack_batch(wins)
+        win = lambda k: wins[k]  # noqa: E731
     dx, dy, dt, doff, dtau = (torch.from_numpy(a).to(dev) for a in (x, y, t, off, tau))
     sensor = ecmd.sensor(s.width, s.height, s.foe)
     ctx = ecmd.Context(0)
@@ -206,7 +239,7 @@ def main():
     P = min(args.plain_windows, B)
     plain_t = []
     for k in range(P):
-        w = wins[k]
+        w = win(k)
         px, py, pt, po, ptau = (torch.from_numpy(a).to(dev) for a in pack_batch([w]))
         ctx.estimate_batched(sensor, px, py, pt, po, ptau, s.d_lo, s.d_hi, s.eps)  # warm
         torch.cuda.synchronize()
@@ -216,6 +249,9 @@ def main():
         plain_t.append(time.perf_counter() - a)
         assert (rp.j_star, rp.K) == (last[k].j_star, last[k].K)
 
+    # measured denominators: conflict-free returning LDS atomics, HBM stream read
+    peaks = ctx.measure_peaks()
+
     # roofline of the evaluation kernel (all its launches in the timed region)
     ops_step = OPS_POINT * pt_ev + OPS_INTERVAL * bd_ev + OPS_PIXEL * pix
     launches = max(prof["eval_launches"], 1)
@@ -224,7 +260,7 @@ def main():
     achieved = ops_launch / avg_launch_s if avg_launch_s > 0 else 0.0
     # each launch must read every event of every window still searching once
     alg_bytes = EVENT_RECORD_BYTES * sum(r.steps * r.n_events for r in last) * args.steps / launches
-    tkey = {"windows": B, "frontier_batch": args.frontier_batch or 64}
+    tkey = {"config": args.config, "windows": B, "frontier_batch": args.frontier_batch or 64}
     roof = {
         "bound": "alu",
         "achieved": round(achieved / 1e9, 1),
@@ -238,8 +274,11 @@ def main():
         "avg_launch_us": round(avg_launch_s * 1e6, 2),
         "launches_per_step": round(launches / args.steps, 2),
         "eval_share_of_step": round(prof["eval_ms"] / 1e3 / args.steps / sec, 3),
-        "lds_atomics_per_s": round((pt_ev + pix) * args.steps / (prof["eval_ms"] / 1e3), 1)
+        # one returning LDS atomic per event and hypothesis (walk steps add more)
+        "lds_atomics_per_s_at_least": round((pt_ev + bd_ev) * args.steps / (prof["eval_ms"] / 1e3), 1)
         if prof["eval_ms"] > 0 else None,
+        "lds_atomic_peak_measured": round(peaks["lds_atomics_per_s"], 1),
+        "hbm_read_peak_measured_GBps": round(peaks["hbm_read_bytes_per_s"] / 1e9, 1),
     }
 
     out = {
@@ -256,8 +295,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{B} windows of the 346x260 config per step: 100k events/0.25 s window, "
-                        f"D in [0,1.5], eps 1e-5 (L=18), batched certified BnB",
+            "workload": WORKLOADS[args.config].format(B=B),
             "windows_per_step": B,
             "events_per_window": int(n_w.mean()),
             "eps": s.eps,
@@ -283,25 +321,33 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
+        # the smallest windows of the batch (all c2 windows have 100k events)
+        order = np.argsort(np.diff(off), kind="stable")
         nc = max(1, min(args.cpu_windows, B))
         t_cpu = 0.0
         ev_cpu = 0
-        for k in range(nc):
-            w = wins[k]
+        dev64 = []
+        for k in (int(v) for v in order[:nc]):
+            w = win(k)
             a = time.perf_counter()
             o = O.bnb(O.Events.of_window(w), s.d_lo, s.d_hi, s.eps)
             t_cpu += time.perf_counter() - a
             ev_cpu += (o.point_evals + o.bound_evals) * w.n
             assert (o.j_star, o.K) == (last[k].j_star, last[k].K), "GPU and oracle optima differ"
+            if len(dev64) < 2:  # the same method in fp64 arithmetic, for |D_gpu - D_fp64|
+                _, d64 = O.bnb64(O.Events.of_window(w), s.d_lo, s.d_hi, s.eps)
+                dev64.append(abs(float(last[k].d_hat) - d64))
         out["cpu_baseline"] = {
             "value": round(ev_cpu / t_cpu, 1),
             "unit": "event-hypothesis evals/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"{nc} of the step's windows, canonical BnB, single thread "
+            "sample": f"{nc} of the step's windows (the smallest), canonical BnB, single thread "
                       f"({t_cpu:.1f} s, {nc / t_cpu:.3f} windows/s)",
             "windows_per_s": round(nc / t_cpu, 4),
         }
+        out["fp64_check"] = {"windows": len(dev64), "max_abs_d_gpu_minus_d_fp64": max(dev64),
+                             "eps": s.eps}
     print(json.dumps(out), flush=True)
     if net is not None:
         net.close()

@@ -692,6 +692,49 @@ int ecmd_plan(const ecmd_sensor* sensor, const ecmd_search* search, int32_t pola
     return ECMD_OK;
 }
 
+int ecmd_measure_peaks(ecmd_ctx* c, int64_t hbm_bytes, double* lds_atomics_per_s, double* hbm_read_bytes_per_s) {
+    if (!c || hbm_bytes < 0 || !lds_atomics_per_s || !hbm_read_bytes_per_s) return ECMD_EINVAL;
+    c->err.clear();
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long bytes = (hbm_bytes ? hbm_bytes : (4ll << 30)) & ~255ll;
+    if (bytes < (1ll << 20)) return fail(c, ECMD_EINVAL, "hbm_bytes must be at least 1 MiB");
+    const int lds_blocks = c->num_cu * 2, iters = 4096;
+    const int hbm_blocks = c->num_cu * 8;
+    HIPCHK(c, c->misc.ensure(sizeof(float) * (size_t)std::max(lds_blocks, hbm_blocks)));
+    DevBuf big;
+    hipError_t e = big.ensure((size_t)bytes);
+    if (e != hipSuccess) return fail(c, ECMD_ENOMEM, "cannot allocate %lld bytes", bytes);
+    e = hipMemsetAsync(big.p, 0, (size_t)bytes, c->stream);  // first touch outside the timing
+    hipEvent_t a = nullptr, b = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    double best_lds = 0.0, best_hbm = 0.0;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        float ms = 0.0f;
+        e = hipEventRecord(a, c->stream);
+        if (e == hipSuccess) e = launch_lds_atomics(c->stream, lds_blocks, iters, c->misc.as<unsigned>());
+        if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms > 0.0f && rep > 0)
+            best_lds = std::max(best_lds, (double)lds_blocks * 1024.0 * iters / (ms * 1e-3));
+        if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+        if (e == hipSuccess) e = launch_stream_read(c->stream, big.p, bytes, hbm_blocks, c->misc.as<float>());
+        if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess && ms > 0.0f && rep > 0) best_hbm = std::max(best_hbm, (double)bytes / (ms * 1e-3));
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(c->stream);
+    big.release();
+    HIPCHK(c, e);
+    *lds_atomics_per_s = best_lds;
+    *hbm_read_bytes_per_s = best_hbm;
+    return ECMD_OK;
+}
+
 float ecmd_grid_point(float d_lo, float d_hi, uint32_t L, uint32_t j) {
     if (L < 1 || L > 30 || j > (1u << L)) return NAN;
     return host_grid_d(d_lo, d_hi, (int)L, j);

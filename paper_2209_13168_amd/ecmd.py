@@ -128,6 +128,7 @@ def _load():
         "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
         "ecmd_plan": ([C.POINTER(Sensor), C.POINTER(SearchS), i32, i64, i32, C.POINTER(PlanInfo)], C.c_int),
         "ecmd_grid_point": ([f32, f32, u32, u32], f32),
+        "ecmd_measure_peaks": ([vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_set_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_ctx_get_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_autotune": ([vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32, C.POINTER(SearchS), u32,
@@ -328,6 +329,12 @@ class Context:
         p = ProfileS()
         self._check(lib().ecmd_ctx_get_profile(self.h, C.byref(p), 1 if reset else 0))
         return {f[0]: getattr(p, f[0]) for f in ProfileS._fields_}
+
+    def measure_peaks(self, hbm_bytes: int = 0) -> dict:
+        """Measured LDS-atomic rate (lane ops/s) and HBM read bandwidth (B/s)."""
+        lds, hbm = C.c_double(), C.c_double()
+        self._check(lib().ecmd_measure_peaks(self.h, int(hbm_bytes), C.byref(lds), C.byref(hbm)))
+        return {"lds_atomics_per_s": lds.value, "hbm_read_bytes_per_s": hbm.value}
 
     # ---------------------------------------------------------- estimation
     def estimate(self, sensor: Sensor, x, y, t, t0: float, t1: float, d_lo: float, d_hi: float, eps: float,

@@ -106,3 +106,40 @@ def test_network_outliving_its_context_is_rejected_not_used():
     assert ecmd.lib().ecmd_cnn_train_step(h, img.ctypes.data, out.ctypes.data, 1, C.c_float(1e-3), 0, None) == ecmd.EINVAL
     net.close()  # frees the empty handle
     assert net.h is None
+
+
+def test_trained_network_gains_on_held_out_windows(ctx):
+    """The committed proposal network on held-out 346x260 windows (never
+    trained on): its error against the certified optimum beats a constant
+    guess by a wide margin, the certified optimum is the same with and without
+    its seeds, and the node counts with and without them are reported."""
+    import os
+
+    import torch
+
+    from paper_2209_13168_amd import ecmd, learned
+
+    path = os.path.join(os.path.dirname(learned.__file__), "weights", "cnn_c2.npz")
+    assert os.path.exists(path), "trained weights are missing"
+    net, meta = learned.load(ctx, path)
+    wins = config_windows("c4", range(learned.HELD_OUT + 5000, learned.HELD_OUT + 5064))
+    s = wins[0].spec
+    dev = torch.device("cuda:0")
+    x, y, t, off, tau = (torch.from_numpy(a).to(dev) for a in pack_batch(wins))
+    sen = ecmd.sensor(*learned.SENSOR)
+    plain = ctx.estimate_batched(sen, x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    seeded = ctx.estimate_learned(net, sen, x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    assert [(r.j_star, r.K) for r in plain] == [(r.j_star, r.K) for r in seeded]
+    assert all(r.seeded == 1 for r in seeded)
+    imgs = ctx.downsample(sen, x, y, off).cpu().numpy().view(np.uint16).reshape(len(wins), -1)
+    pred = net.forward(imgs)
+    lab = np.array([r.d_hat for r in plain])
+    err = np.abs(pred - lab).mean()
+    const = np.abs(np.median(lab) - lab).mean()
+    n_plain = np.mean([r.nodes_expanded for r in plain])
+    n_seed = np.mean([r.nodes_expanded for r in seeded])
+    print(f"network |d - d_hat| {err:.4f} (constant guess {const:.4f}); nodes per window "
+          f"{n_plain:.1f} without seeds, {n_seed:.1f} with")
+    assert err < 0.05 and err < 0.25 * const
+    assert n_seed <= 1.02 * n_plain
+    net.close()
