@@ -168,7 +168,7 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
  * further, trading guest copies for occupancy).  graph: replay the step
  * loop as a captured hipGraph (0 = plain launches).  group: hypotheses of
  * one window and tile evaluated per work item (0 = chosen from the batch
- * size so that each CU still gets ~48 items: 1 up to ~16 windows of 346x260, then more). */
+ * size: 1 while there are fewer than ~48 items per CU, else 2). */
 typedef struct {
     int32_t frontier_batch;
     int32_t tile_px;

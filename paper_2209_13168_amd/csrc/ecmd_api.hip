@@ -70,6 +70,7 @@ constexpr int kChunk = 4096;          // events per prep workgroup
 constexpr int kDefaultF = 64;         // nodes expanded together
 constexpr int kDefaultCap = 16384;    // queued nodes per window
 constexpr int kMaxSteps = 1 << 20;    // hard stop of the step loop
+constexpr int kMaxRebins = 4;         // re-binnings of the events per search
 
 }  // namespace
 
@@ -316,9 +317,11 @@ static double key_to_double(long long hi, unsigned long long lo) {
 // --------------------------------------------------------------- pipeline
 
 // Prep of B windows: window params, event binning.  Needs h_off (host copy
-// of the offsets) and h_tau.
+// of the offsets) and h_tau.  rebin: keep the window params already on the
+// device (binning ranges narrowed to the live search).  copies_out: event
+// records written, guest copies included.
 static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, float d_lo, float d_hi,
-                    int* nblk_out) {
+                    int* nblk_out, bool rebin = false, long long* copies_out = nullptr) {
     const int T = g.T;
     std::vector<int> blk(B + 1, 0);
     for (int w = 0; w < B; ++w) {
@@ -339,7 +342,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     HIPCHK(c, c->err_flag.ensure(sizeof(int)));
     HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream));
     HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
-    HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
+    if (!rebin) HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
     // count + scan (scatter needs the total to size the event store)
     HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
@@ -360,6 +363,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
                           nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
                           c->ev.as<float4>(), nullptr));
     *nblk_out = nblk;
+    if (copies_out) *copies_out = total;
     return ECMD_OK;
 }
 
@@ -401,11 +405,14 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
     Timers tm(c);
     int nblk = 0;
+    long long copies = 0;
     tm.begin();
-    int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk);
+    int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk, false, &copies);
     if (rc) return rc;
     tm.end(2);
     tm.cut();
+    const long long n_events = c->h_off[B] - c->h_off[0];
+    int rebins = 0;
 
     Search sp;
     sp.d_lo = search->d_lo;
@@ -419,13 +426,14 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     const int T = g.T;
-    // hypotheses per work item: fewer set-ups, but still ~48 items per CU so
-    // that the launch does not end on a few long items (measured: 2 for 32
-    // windows of 346x260, 1 for 8 or fewer)
+    // hypotheses per work item: two once there are ~48 items per CU, else
+    // one (measured: 2 is best for 32 windows of 346x260 and for the
+    // 256-window 1280x720 batch, 1 for 8 windows or fewer; larger groups
+    // save set-ups but leave launches ending on a few long items)
     {
         const long long work = (long long)B * sp.HS * T;
         const long long slots = (long long)c->num_cu * 48;
-        sp.G = (int)std::max(1ll, std::min(8ll, work / std::max(slots, 1ll)));
+        sp.G = (int)std::max(1ll, std::min(2ll, work / std::max(slots, 1ll)));
         if (c->tune.group > 0) sp.G = std::min(c->tune.group, 64);
     }
     HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
@@ -511,6 +519,21 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         active = B + *h_active;  // n_active counts finished windows down from zero
+        // Events copied to several tiles (guests) are binned by the whole
+        // search range; once the frontier has narrowed, bin again with each
+        // window's live range (kMaxRebins times at most) to drop copies no
+        // longer needed.
+        if (active > 0 && rebins < kMaxRebins && copies > n_events + n_events / 100) {
+            tm.begin();
+            HIPCHK(c, launch_live_range(c->stream, sp, c->state.as<WinState>(), c->front.as<Node>(),
+                                        c->sel.as<Sel>(), c->wp.as<WinParam>(), B));
+            rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk, true, &copies);
+            if (rc) return rc;
+            h_active = (int*)c->pinned.p;  // run_prep stages through the same buffer
+            tm.end(2);
+            tm.cut();
+            ++rebins;
+        }
     }
     std::vector<WinState> hs(B);
     HIPCHK(c, hipMemcpyAsync(hs.data(), c->state.p, sizeof(WinState) * B, hipMemcpyDeviceToHost, c->stream));

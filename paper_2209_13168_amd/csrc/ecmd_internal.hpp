@@ -187,6 +187,11 @@ hipError_t launch_cnn_reduce(hipStream_t s, const float* pg, const float* lossb,
 hipError_t launch_adam(hipStream_t s, float* P, float* m, float* v, const float* grad, float lr, int step);
 hipError_t launch_seed_from_pred(hipStream_t s, const float* pred, int B, float d_lo, float d_hi, float* seeds);
 
+// the live grid range of every active window (queued and selected nodes)
+// as its binning range r_lo, r_hi
+hipError_t launch_live_range(hipStream_t s, const Search& sp, const WinState* st, const Node* front, const Sel* sel,
+                             WinParam* wp, int B);
+
 // calibration (roofline denominators measured on the device)
 hipError_t launch_lds_atomics(hipStream_t s, int blocks, int iters, unsigned* sink);
 hipError_t launch_stream_read(hipStream_t s, const void* a, long long bytes, int blocks, float* partial);

@@ -990,6 +990,53 @@ __global__ __launch_bounds__(NTF) void k_frontier(
               s_wave);
 }
 
+// Grid range still alive in each active window: the queued nodes and those
+// selected for the next step.  Every later hypothesis is a grid interval or
+// point inside it and the warp is monotone in d, so events binned with this
+// range still reach every tile they can reach for the rest of the search;
+// binning again with it drops the guest copies that only the early, wide
+// intervals needed.
+__global__ __launch_bounds__(NTF) void k_live_range(Search sp, const WinState* __restrict__ st,
+                                                    const Node* __restrict__ front, const Sel* __restrict__ sel,
+                                                    WinParam* __restrict__ wp) {
+    const int w = blockIdx.x, tid = threadIdx.x;
+    __shared__ unsigned s_lo, s_hi;
+    const WinState s = st[w];
+    if (!s.active) return;
+    if (tid == 0) {
+        s_lo = 0xFFFFFFFFu;
+        s_hi = 0u;
+    }
+    __syncthreads();
+    const Node* fr = front + (long long)w * sp.CAP;
+    const Sel* sl = sel + (long long)w * sp.F;
+    unsigned lo = 0xFFFFFFFFu, hi = 0u;
+    for (int i = tid; i < s.n_front; i += NTF) {
+        lo = min(lo, fr[i].ja);
+        hi = max(hi, fr[i].jb);
+    }
+    for (int i = tid; i < s.n_sel; i += NTF) {
+        lo = min(lo, sl[i].ja);
+        hi = max(hi, sl[i].jb);
+    }
+    atomicMin(&s_lo, lo);
+    atomicMax(&s_hi, hi);
+    __syncthreads();
+    if (tid == 0 && s_lo <= s_hi) {
+        WinParam p = wp[w];
+        p.r_lo = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, s_lo), p.tau);
+        p.r_hi = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, s_hi), p.tau);
+        wp[w] = p;
+    }
+}
+
+hipError_t launch_live_range(hipStream_t s, const Search& sp, const WinState* st, const Node* front, const Sel* sel,
+                             WinParam* wp, int B) {
+    if (B <= 0) return hipSuccess;
+    k_live_range<<<B, NTF, 0, s>>>(sp, st, front, sel, wp);
+    return hipGetLastError();
+}
+
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active) {
