@@ -56,11 +56,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "6a4a1e447c0dd5fc60cd8c24ae4e68f9628d870d78a0b74d79261248058f1807",
+    "sources_sha256": "aa3b794df85545c167a90c8f87bc734298a01f47bb312868bc684415d742c2d2",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
-    "fetch_kib": 28114.0,
-    "write_kib": 457.8,
-    "fetch_bytes_per_kib": 1073741824 / 524304.7,
+    "fetch_kib": 28184.3,
+    "write_kib": 457.7,
+    "fetch_bytes_per_kib": 1073741824 / 524304.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
