@@ -883,13 +883,16 @@ __global__ __launch_bounds__(NTF) void k_frontier(
     }
     unsigned jdummy = 0;
     block_argmax(best_gap, jdummy, s_hi, s_lo, s_j);
+    // the gap classes from the largest down, one thread each: `before` =
+    // improvable nodes in larger classes, n_keep = all of them
+    const int hb = tid < 130 ? s_hist[129 - tid] : 0;
+    int n_keep = 0;
+    const int before = block_scan(hb, s_wave, n_keep);
     if (tid == 0) {
         s.bound_evals += s_nbound;
         s.event_hyp += s_nbound * p.n_events;
         s.pixel_updates += (long long)s_pix;
         s.nodes_pruned += s_pruned;
-        int n_keep = 0;
-        for (int b = 0; b < 130; ++b) n_keep += s_hist[b];
         int stop = 0;
         if (overflow) {
             s.status = -5;  // ECMD_EFRONTIER
@@ -917,18 +920,15 @@ __global__ __launch_bounds__(NTF) void k_frontier(
                 take = (int)left;
             }
         }
-        // take every node of a larger gap class and the first `quota` of class b*
-        int cum = 0, bstar = 0, quota = 0;
-        if (!stop) {
-            for (int b = 129; b >= 0; --b) {
-                if (cum + s_hist[b] >= take) { bstar = b; quota = take - cum; break; }
-                cum += s_hist[b];
-            }
-        }
-        s_bstar = bstar;
-        s_quota = quota;
         s_stop = stop;
         s_take = take;
+    }
+    __syncthreads();
+    // take every node of a larger gap class and the first `quota` of class
+    // b*, the class where the running count reaches `take`
+    if (!s_stop && tid < 130 && before < s_take && s_take <= before + hb) {
+        s_bstar = 129 - tid;
+        s_quota = s_take - before;
     }
     __syncthreads();
     if (s_stop) {
