@@ -616,27 +616,47 @@ __device__ __forceinline__ int block_scan(int v, int* s_wave, int& total) {
     return base + x - v;
 }
 
-// Lexicographic maximum of (K, -j) over the workgroup.
+// Lexicographic maximum of (K, -j) over the workgroup: within each wave by
+// lane exchanges, then across the NWF wave winners through LDS.
+__device__ __forceinline__ bool lex_better(long long bh, unsigned long long bl, unsigned bj, long long ah,
+                                           unsigned long long al, unsigned aj) {
+    return bh > ah || (bh == ah && (bl > al || (bl == al && bj < aj)));
+}
+
 __device__ __forceinline__ void block_argmax(i128& K, unsigned& j, long long* s_hi, unsigned long long* s_lo,
                                              unsigned* s_j) {
-    const int tid = threadIdx.x;
-    sp128(K, s_hi[tid], s_lo[tid]);
-    s_j[tid] = j;
-    __syncthreads();
-    for (int o = NTF / 2; o > 0; o >>= 1) {
-        if (tid < o) {
-            const i128 a = mk128(s_hi[tid], s_lo[tid]), b = mk128(s_hi[tid + o], s_lo[tid + o]);
-            const unsigned ja = s_j[tid], jb = s_j[tid + o];
-            if (b > a || (b == a && jb < ja)) {
-                s_hi[tid] = s_hi[tid + o];
-                s_lo[tid] = s_lo[tid + o];
-                s_j[tid] = jb;
-            }
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    long long h;
+    unsigned long long l;
+    sp128(K, h, l);
+    unsigned jj = j;
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long oh = __shfl_xor(h, o, 64);
+        const unsigned long long ol = __shfl_xor(l, o, 64);
+        const unsigned oj = __shfl_xor(jj, o, 64);
+        if (lex_better(oh, ol, oj, h, l, jj)) {
+            h = oh;
+            l = ol;
+            jj = oj;
         }
-        __syncthreads();
     }
-    K = mk128(s_hi[0], s_lo[0]);
-    j = s_j[0];
+    if (lane == 0) {
+        s_hi[wave] = h;
+        s_lo[wave] = l;
+        s_j[wave] = jj;
+    }
+    __syncthreads();
+    h = s_hi[0];
+    l = s_lo[0];
+    jj = s_j[0];
+    for (int k = 1; k < NWF; ++k)
+        if (lex_better(s_hi[k], s_lo[k], s_j[k], h, l, jj)) {
+            h = s_hi[k];
+            l = s_lo[k];
+            jj = s_j[k];
+        }
+    K = mk128(h, l);
+    j = jj;
     __syncthreads();
 }
 
