@@ -1,7 +1,7 @@
 """CPU statement of the learned-incumbent network (fp64, PyTorch CPU ops).
 
 TEST INFRASTRUCTURE ONLY.  The network is not in the paper: it proposes a
-starting incumbent for Algorithm 1 (the branch and bound stays the judge).
+starting incumbent for Algorithm 1 (the branch and bound still certifies the optimum).
 
 Definition (parameters as one fp32 vector, layout below):
   x0 = image (64x64, values already bfloat16)
