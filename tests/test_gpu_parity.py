@@ -290,3 +290,25 @@ def test_search_is_reproducible(ctx):
     runs = [ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4) for _ in range(3)]
     key = lambda rs: [(r.j_star, r.K, r.nodes_expanded, r.bound_evals, r.pixel_updates, r.steps) for r in rs]
     assert key(runs[0]) == key(runs[1]) == key(runs[2])
+
+
+def test_measured_peaks_are_plausible(ctx):
+    """The calibration kernels run and give rates within the chip's reach
+    (returning LDS atomics under 32 banks x 2.4 GHz x 256 CUs; HBM read
+    under the 8 TB/s specification)."""
+    p = ctx.measure_peaks(1 << 30)
+    assert 1e11 < p["lds_atomics_per_s"] < 256 * 64 * 2.4e9 * 1.05
+    assert 5e11 < p["hbm_read_bytes_per_s"] < 8.2e12
+
+
+def test_host_plan_matches_the_device_search(ctx):
+    """ecmd_plan (host only) gives the grid depth the device search uses."""
+    from paper_2209_13168_amd import ecmd
+
+    w = config_windows("c2", [5], n_events=5000)[0]
+    s = w.spec
+    x, y, t, off, tau = pack_batch([w])
+    r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)[0]
+    p = ecmd.plan(_sensor(s), s.d_lo, s.d_hi, s.eps)
+    assert r.L == p["L"] and p["segments"] == 4
+    assert r.d_hat == np.float32(ecmd.grid_point(s.d_lo, s.d_hi, p["L"], r.j_star))
