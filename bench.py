@@ -56,10 +56,10 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "aa3b794df85545c167a90c8f87bc734298a01f47bb312868bc684415d742c2d2",
+    "sources_sha256": "f61147a9f175e2492c6d5eb9da83dc9a1ea144f6491cb96155358330ef86a2db",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
-    "fetch_kib": 28184.3,
-    "write_kib": 457.7,
+    "fetch_kib": 27863.8,
+    "write_kib": 457.5,
     "fetch_bytes_per_kib": 1073741824 / 524304.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
