@@ -268,6 +268,65 @@ int ecmd_estimate_stream(ecmd_ctx *ctx, const ecmd_sensor *sensor, const ecmd_ev
                          double t_start, double tau, int32_t K, const ecmd_search *search,
                          uint32_t flags, ecmd_result *out);
 
+/* --------------------------------------------------- asynchronous batches */
+
+/* A plan holds every device buffer of batched searches up to fixed limits,
+ * so that ecmd_plan_launch only enqueues kernels on the context's stream:
+ * it allocates nothing, copies nothing between host and device and never
+ * waits, and a caller may capture it into a hipGraph and replay it.  The
+ * checks that the synchronous batched call makes on the host are made on
+ * the device, per window; a fixed number of frontier steps (Algorithm 1's
+ * loop, four per block) replaces the host's polling of the search.
+ *   max_windows: B of a launch, 1 .. 65535;
+ *   max_steps:   frontier steps per launch, rounded up to a multiple of 4
+ *                (0 = 256); each costs two kernel launches, which return
+ *                at once for finished windows;
+ *   max_events:  events of a launch over all windows, 1 .. 2^40;
+ *   max_records: binned event records, guest copies included (0 = the worst
+ *                case: max_events times the tiles of one FOE quadrant);
+ *   polarity:    non-zero: launches take polarities (the contrast over
+ *                2*W*H cells, as ecmd_estimate_divergence_batched_polarity). */
+typedef struct {
+    int32_t max_windows;
+    int32_t max_steps;
+    int64_t max_events;
+    int64_t max_records;
+    int32_t polarity;
+    int32_t reserved;
+} ecmd_plan_limits;
+
+typedef struct ecmd_batch_plan ecmd_batch_plan;
+
+/* Allocate a plan on the context for `sensor` and `search` (both copied;
+ * the context's tuning at this call applies).  `limits` is read, and its
+ * zero fields are replaced by the values used.  The plan's device memory is
+ * freed by ecmd_plan_destroy, or with the context: the handle then accepts
+ * only ecmd_plan_destroy. */
+int ecmd_plan_create(ecmd_ctx *ctx, const ecmd_sensor *sensor, const ecmd_search *search,
+                     ecmd_plan_limits *limits, ecmd_batch_plan **out);
+
+/* Enqueue the batched search of B windows: arguments as
+ * ecmd_estimate_divergence_batched, every array a device pointer, polarity
+ * non-NULL exactly when the plan has limits.polarity.  The results reach
+ * out[0..B) (device memory, or pinned host memory the device can write)
+ * when the stream gets there; they equal the synchronous call's, except:
+ * out[w].status = ECMD_EINVAL (other fields zero) for a window that fails
+ * the synchronous call's checks (offsets, event count, tau, d_hi * tau,
+ * an event with a non-finite coordinate or t_rel outside [0, tau[w]]),
+ * and for every window when the valid ones hold more than max_events
+ * events; ECMD_ENOMEM for every window when the binned records exceed
+ * max_records; ECMD_EBUDGET, with the incumbent and its certified gap, for a
+ * window still searching after max_steps steps.  Returns a call-level error
+ * only: NULL arrays, B outside 1 .. max_windows, a launch failure.  Launches
+ * of one plan share its buffers: they must not overlap (one stream orders
+ * them). */
+int ecmd_plan_launch(ecmd_batch_plan *plan, const float *x, const float *y, const float *t_rel,
+                     const int8_t *polarity, const int64_t *offsets, const float *tau, int32_t B,
+                     const float *d_seeds, ecmd_result *out);
+
+/* Free the plan (waits for the context's stream first). */
+void ecmd_plan_destroy(ecmd_batch_plan *plan);
+
 /* -------------------------------------------------------------- probes */
 
 /* Pixel index ky*W + kx of every event at divergence d (-1 = outside),

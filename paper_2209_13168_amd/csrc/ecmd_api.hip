@@ -79,6 +79,7 @@ struct ecmd_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     std::vector<ecmd_cnn*> nets;  // live networks created on this context
+    std::vector<ecmd_batch_plan*> plans;  // live plans created on this context
     int num_cu = 0;
     size_t max_lds = 0;
     size_t eval_lds = 0;   // LDS bytes of the last evaluation set-up (0 = none yet)
@@ -331,7 +332,8 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     const int nblk = blk[B];
     HIPCHK(c, c->wp.ensure(sizeof(WinParam) * std::max(B, 1)));
     HIPCHK(c, c->blk.ensure(sizeof(int) * (B + 1)));
-    HIPCHK(c, c->pinned.ensure(sizeof(int) * (B + 1) + 64));
+    // staging of blk (B + 1 ints) and, later, of the total and B error flags
+    HIPCHK(c, c->pinned.ensure(sizeof(int) * B + 72));
     memcpy(c->pinned.p, blk.data(), sizeof(int) * (B + 1));
     HIPCHK(c, hipMemcpyAsync(c->blk.p, c->pinned.p, sizeof(int) * (B + 1), hipMemcpyHostToDevice, c->stream));
     const size_t nctr = prep_counters(B, T);
@@ -339,29 +341,31 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     HIPCHK(c, c->seg_off.ensure(sizeof(long long) * (B * T + 1)));
     HIPCHK(c, c->seg_own.ensure(sizeof(int) * B * T));
     HIPCHK(c, c->cursor.ensure(sizeof(unsigned long long) * nctr));
-    HIPCHK(c, c->err_flag.ensure(sizeof(int)));
+    HIPCHK(c, c->err_flag.ensure(sizeof(int) * B));
     HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream));
-    HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int) * B, c->stream));
     if (!rebin) HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
     // count + scan (scatter needs the total to size the event store)
     HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
-                          c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>()));
+                          c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>(), -1));
     HIPCHK(c, hipMemcpyAsync(c->pinned.p, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
                              hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync((char*)c->pinned.p + 8, c->err_flag.p, sizeof(int), hipMemcpyDeviceToHost,
+    HIPCHK(c, hipMemcpyAsync((char*)c->pinned.p + 8, c->err_flag.p, sizeof(int) * B, hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const long long total = *(long long*)c->pinned.p;
-    const int errf = *(int*)((char*)c->pinned.p + 8);
-    if (errf)
-        return fail(c, ECMD_EINVAL, "an event has a non-finite coordinate or t_rel outside [0, tau]");
+    const int* errf = (const int*)((char*)c->pinned.p + 8);
+    for (int w = 0; w < B; ++w)
+        if (errf[w])
+            return fail(c, ECMD_EINVAL, "window %d: an event has a non-finite coordinate or t_rel outside [0, tau]",
+                        w);
     // one stride of padding: the evaluation kernel prefetches up to
     // kEvalThreads records past the end of a segment
     HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)(total + kEvalThreads)));
     HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
-                          c->ev.as<float4>(), nullptr));
+                          c->ev.as<float4>(), nullptr, -1));
     *nblk_out = nblk;
     if (copies_out) *copies_out = total;
     return ECMD_OK;
@@ -391,6 +395,18 @@ static hipError_t eval_setup(ecmd_ctx* c, size_t lds, int* nb) {
     }
     *nb = c->eval_nb;
     return hipSuccess;
+}
+
+// Hypotheses per work item for B windows: two once there are ~48 items per
+// CU, else one (measured: 2 is best for 32 windows of 346x260 and for the
+// 256-window 1280x720 batch, 1 for 8 windows or fewer; larger groups save
+// set-ups but leave launches ending on a few long items), unless the
+// context's tuning fixes it.
+static int group_for(ecmd_ctx* c, int B, const Search& sp, int T) {
+    if (c->tune.group > 0) return std::min(c->tune.group, 64);
+    const long long work = (long long)B * sp.HS * T;
+    const long long slots = (long long)c->num_cu * 48;
+    return (int)std::max(1ll, std::min(2ll, work / std::max(slots, 1ll)));
 }
 
 // Whole batched search on staged inputs; fills out[0..B).
@@ -426,16 +442,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     const int T = g.T;
-    // hypotheses per work item: two once there are ~48 items per CU, else
-    // one (measured: 2 is best for 32 windows of 346x260 and for the
-    // 256-window 1280x720 batch, 1 for 8 windows or fewer; larger groups
-    // save set-ups but leave launches ending on a few long items)
-    {
-        const long long work = (long long)B * sp.HS * T;
-        const long long slots = (long long)c->num_cu * 48;
-        sp.G = (int)std::max(1ll, std::min(2ll, work / std::max(slots, 1ll)));
-        if (c->tune.group > 0) sp.G = std::min(c->tune.group, 64);
-    }
+    sp.G = group_for(c, B, sp, T);
     HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
     HIPCHK(c, c->front.ensure(sizeof(Node) * (size_t)B * sp.CAP));
     HIPCHK(c, c->sel.ensure(sizeof(Sel) * (size_t)B * sp.F));
@@ -451,7 +458,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
                           c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(), qcap, &q[0],
-                          T, c->seg_off.as<long long>()));
+                          T, c->seg_off.as<long long>(), InitCheck{nullptr, nullptr, 0}));
     const size_t lds = eval_lds_bytes(g.max_tile_px);
     int nb = 0;
     HIPCHK(c, eval_setup(c, lds, &nb));
@@ -632,6 +639,51 @@ static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, 
     return run_search(c, sensor, in, B, search, L, out);
 }
 
+
+// ------------------------------------------------------- asynchronous plan
+
+// Device buffers of batched searches up to fixed limits; a launch only
+// enqueues kernels (no allocation, host copy or wait), so it can be
+// captured into a graph and replayed.
+struct ecmd_batch_plan {
+    ecmd_ctx* ctx = nullptr;  // NULL once the context is destroyed
+    ecmd_sensor sensor{};
+    ecmd_search search{};
+    ecmd_plan_limits lim{};
+    Geometry g{};
+    Search sp{};      // G is set per launch
+    int nblk_max = 0;  // prep workgroups of the largest launch
+    int qcap = 0;
+    size_t lds = 0;
+    int nb = 0;
+    DevBuf wp, blk, cnt, seg_off, seg_own, cursor, ev, werr, wstat, state, front, sel, hyps, act, items, queues, part,
+        n_active;
+};
+
+static void plan_release(ecmd_batch_plan* p) {
+    DevBuf* bufs[] = {&p->wp,    &p->blk,  &p->cnt,  &p->seg_off, &p->seg_own, &p->cursor, &p->ev,
+                      &p->werr,  &p->wstat, &p->state, &p->front,  &p->sel,     &p->hyps,   &p->act,
+                      &p->items, &p->queues, &p->part, &p->n_active};
+    for (DevBuf* b : bufs) b->release();
+}
+
+
+// The prep of a launch: clear the counters, count + scan, scatter (at most
+// p->lim.max_records records).
+static hipError_t plan_prep(ecmd_batch_plan* p, hipStream_t s, const float* x, const float* y, const float* t,
+                            const signed char* pol, const long long* off, int B) {
+    const Geometry& g = p->g;
+    hipError_t e = launch_fill_u32(s, p->cnt.as<unsigned>(), (long long)prep_counters(B, g.T), 0u);
+    if (e != hipSuccess) return e;
+    e = launch_prep(s, 0, g, x, y, t, pol, off, p->wp.as<WinParam>(), B, p->blk.as<int>(), p->nblk_max, kChunk,
+                    p->cnt.as<int>(), p->seg_off.as<long long>(), p->seg_own.as<int>(),
+                    p->cursor.as<unsigned long long>(), nullptr, p->werr.as<int>(), -1);
+    if (e != hipSuccess) return e;
+    return launch_prep(s, 1, g, x, y, t, pol, off, p->wp.as<WinParam>(), B, p->blk.as<int>(), p->nblk_max, kChunk,
+                       nullptr, p->seg_off.as<long long>(), nullptr, p->cursor.as<unsigned long long>(),
+                       p->ev.as<float4>(), nullptr, p->lim.max_records);
+}
+
 // ------------------------------------------------------------------ ABI
 
 extern "C" {
@@ -674,10 +726,14 @@ void ecmd_ctx_destroy(ecmd_ctx* c) {
                       &c->front, &c->sel, &c->hyps, &c->act, &c->items, &c->queues, &c->part, &c->n_active, &c->pix,
                       &c->img, &c->keep, &c->counts, &c->misc};
     for (DevBuf* b : bufs) b->release();
-    // networks outlive their context only as empty handles
+    // networks and plans outlive their context only as empty handles
     for (ecmd_cnn* n : c->nets) {
         cnn_release(n);
         n->ctx = nullptr;
+    }
+    for (ecmd_batch_plan* p : c->plans) {
+        plan_release(p);
+        p->ctx = nullptr;
     }
     c->pinned.release();
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -857,6 +913,164 @@ int ecmd_estimate_divergence_batched_polarity(ecmd_ctx* c, const ecmd_sensor* se
     if (!c) return ECMD_EINVAL;
     if (!polarity && B > 0) return fail(c, ECMD_EINVAL, "polarity is NULL");
     return batched_impl(c, sensor, x, y, t_rel, polarity, offsets, tau, B, search, flags, d_seeds, out);
+}
+
+int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* search, ecmd_plan_limits* lim,
+                     ecmd_batch_plan** out) {
+    if (!c || !out) return ECMD_EINVAL;
+    c->err.clear();
+    *out = nullptr;
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    int L = 0;
+    rc = check_search(c, search, &L);
+    if (rc) return rc;
+    if (!lim) return fail(c, ECMD_EINVAL, "limits is NULL");
+    if (lim->max_windows < 1 || lim->max_windows > 65535)
+        return fail(c, ECMD_EINVAL, "max_windows = %d out of range 1 .. 65535", lim->max_windows);
+    if (lim->max_events < 1 || lim->max_events > (1ll << 40))
+        return fail(c, ECMD_EINVAL, "max_events = %lld out of range 1 .. 2^40", (long long)lim->max_events);
+    if (lim->max_steps < 0 || lim->max_steps > kMaxSteps)
+        return fail(c, ECMD_EINVAL, "max_steps = %d out of range 0 .. %d", lim->max_steps, kMaxSteps);
+    if (lim->max_records < 0) return fail(c, ECMD_EINVAL, "max_records must be >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int W = sensor->width, H = sensor->height;
+    const int npol = lim->polarity ? 2 : 1;
+    Geometry g;
+    const int budget = c->tune.tile_px > 0 ? std::min(c->tune.tile_px, tile_budget(c)) : tile_budget(c);
+    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, npol, g))
+        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
+    ecmd_plan_limits L2 = *lim;
+    if (L2.max_steps == 0) L2.max_steps = 256;
+    L2.max_steps = (L2.max_steps + 3) / 4 * 4;  // whole polling blocks of four steps
+    if (L2.max_records == 0) {
+        // an event's tiles over any range lie in its FOE quadrant (no event
+        // crosses an FOE line), so it has at most that many copies
+        const bool xcut = sensor->foe_x == floorf(sensor->foe_x) && sensor->foe_x > 0.0f && sensor->foe_x < (float)W;
+        const bool ycut = sensor->foe_y == floorf(sensor->foe_y) && sensor->foe_y > 0.0f && sensor->foe_y < (float)H;
+        const long long per = (long long)(xcut ? g.ntx / 2 : g.ntx) * (ycut ? g.nty / 2 : g.nty);
+        L2.max_records = L2.max_events * per;
+    }
+    ecmd_batch_plan* p = new (std::nothrow) ecmd_batch_plan();
+    if (!p) return fail(c, ECMD_ENOMEM, "host allocation failed");
+    p->ctx = c;
+    p->sensor = *sensor;
+    p->search = *search;
+    p->lim = L2;
+    p->g = g;
+    Search& sp = p->sp;
+    sp.d_lo = search->d_lo;
+    sp.d_hi = search->d_hi;
+    sp.L = L;
+    sp.F = search->frontier_batch > 0 ? search->frontier_batch
+                                      : (c->tune.frontier_batch > 0 ? c->tune.frontier_batch : kDefaultF);
+    sp.CAP = search->frontier_capacity > 0 ? search->frontier_capacity : kDefaultCap;
+    sp.HS = 3 * sp.F;
+    sp.max_nodes = search->max_nodes;
+    const long long M = (long long)W * H * npol;
+    sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
+    sp.M = M;
+    sp.G = 1;
+    const int Bm = L2.max_windows, T = g.T;
+    p->nblk_max = (int)((L2.max_events + kChunk - 1) / kChunk) + Bm;
+    p->qcap = ((Bm + kXcd - 1) / kXcd) * sp.HS * T;
+    const size_t nctr = prep_counters(Bm, T);
+    hipError_t e = hipSuccess;
+    auto get = [&](DevBuf& b, size_t bytes) {
+        if (e == hipSuccess) e = b.ensure(bytes);
+    };
+    get(p->wp, sizeof(WinParam) * Bm);
+    get(p->blk, sizeof(int) * (Bm + 1));
+    get(p->cnt, sizeof(int) * nctr);
+    get(p->seg_off, sizeof(long long) * ((size_t)Bm * T + 1));
+    get(p->seg_own, sizeof(int) * (size_t)Bm * T);
+    get(p->cursor, sizeof(unsigned long long) * nctr);
+    get(p->ev, sizeof(float4) * (size_t)(L2.max_records + kEvalThreads));  // padded as in the synchronous call
+    get(p->werr, sizeof(int) * Bm);
+    get(p->wstat, sizeof(int) * Bm);
+    get(p->state, sizeof(WinState) * Bm);
+    get(p->front, sizeof(Node) * (size_t)Bm * sp.CAP);
+    get(p->sel, sizeof(Sel) * (size_t)Bm * sp.F);
+    get(p->hyps, sizeof(Hyp) * (size_t)Bm * sp.HS);
+    get(p->act, sizeof(int) * (size_t)Bm * sp.HS);
+    get(p->items, sizeof(Item) * (size_t)kXcd * p->qcap);
+    get(p->queues, sizeof(Queue) * 2 * kXcd);
+    get(p->part, sizeof(Part) * (size_t)Bm * sp.HS * T);
+    get(p->n_active, sizeof(int));
+    p->lds = eval_lds_bytes(g.max_tile_px);
+    if (e == hipSuccess) e = eval_setup(c, p->lds, &p->nb);
+    if (e != hipSuccess) {
+        plan_release(p);
+        delete p;
+        HIPCHK(c, e);
+    }
+    c->plans.push_back(p);
+    *lim = L2;
+    *out = p;
+    return ECMD_OK;
+}
+
+int ecmd_plan_launch(ecmd_batch_plan* p, const float* x, const float* y, const float* t_rel, const int8_t* polarity,
+                     const int64_t* offsets, const float* tau, int32_t B, const float* d_seeds, ecmd_result* out) {
+    if (!p) return ECMD_EINVAL;
+    ecmd_ctx* c = p->ctx;
+    if (!c) return ECMD_EINVAL;  // the context is gone
+    c->err.clear();
+    if (B < 1 || B > p->lim.max_windows)
+        return fail(c, ECMD_EINVAL, "B = %d out of range 1 .. %d", B, p->lim.max_windows);
+    if (!x || !y || !t_rel || !offsets || !tau || !out) return fail(c, ECMD_EINVAL, "NULL array argument");
+    if ((polarity != nullptr) != (p->lim.polarity != 0))
+        return fail(c, ECMD_EINVAL, "polarity must be given exactly when the plan was created for it");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const Geometry& g = p->g;
+    const int T = g.T;
+    Search sp = p->sp;
+    sp.G = group_for(c, B, sp, T);
+    const long long* off = (const long long*)offsets;
+    const signed char* pol = (const signed char*)polarity;
+    Queue* q = p->queues.as<Queue>();
+    HIPCHK(c, launch_plan_check(s, off, tau, B, sp.d_hi, g.W, g.H, p->lim.max_events, kChunk, p->wstat.as<int>(),
+                                p->werr.as<int>(), p->blk.as<int>(), q, p->n_active.as<int>()));
+    HIPCHK(c, launch_winparam(s, g, tau, off, B, sp.d_lo, sp.d_hi, p->wp.as<WinParam>()));
+    HIPCHK(c, plan_prep(p, s, x, y, t_rel, pol, off, B));
+    HIPCHK(c, launch_init(s, sp, p->wp.as<WinParam>(), d_seeds, B, p->state.as<WinState>(), p->sel.as<Sel>(),
+                          p->hyps.as<Hyp>(), p->act.as<int>(), p->items.as<Item>(), p->qcap, &q[0], T,
+                          p->seg_off.as<long long>(),
+                          InitCheck{p->wstat.as<int>(), p->werr.as<int>(), (long long)p->lim.max_records}));
+    for (int step = 0; step < p->lim.max_steps; step += 4) {
+        for (int k = 0; k < 4; ++k) {
+            const int parity = k & 1;
+            HIPCHK(c, launch_eval(s, g, p->nb, p->lds, p->ev.as<float4>(), p->seg_off.as<long long>(),
+                                  p->seg_own.as<int>(), p->hyps.as<Hyp>(), p->act.as<int>(), p->items.as<Item>(),
+                                  p->qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd], p->part.as<Part>(), sp.HS,
+                                  nullptr));
+            HIPCHK(c, launch_frontier(s, sp, p->wp.as<WinParam>(), B, T, p->seg_off.as<long long>(),
+                                      p->state.as<WinState>(), p->front.as<Node>(), p->sel.as<Sel>(),
+                                      p->hyps.as<Hyp>(), p->act.as<int>(), p->part.as<Part>(), p->items.as<Item>(),
+                                      p->qcap, &q[(1 - parity) * kXcd], p->n_active.as<int>()));
+        }
+        // bin again with the live ranges, at the synchronous call's polling
+        // points (unconditionally: the host does not see the copy count)
+        if (step / 4 < kMaxRebins && step + 4 < p->lim.max_steps) {
+            HIPCHK(c, launch_live_range(s, sp, p->state.as<WinState>(), p->front.as<Node>(), p->sel.as<Sel>(),
+                                        p->wp.as<WinParam>(), B));
+            HIPCHK(c, plan_prep(p, s, x, y, t_rel, pol, off, B));
+        }
+    }
+    HIPCHK(c, launch_plan_results(s, sp, B, p->state.as<WinState>(), off, tau, out));
+    return ECMD_OK;
+}
+
+void ecmd_plan_destroy(ecmd_batch_plan* p) {
+    if (!p) return;
+    if (ecmd_ctx* c = p->ctx) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        plan_release(p);
+        c->plans.erase(std::remove(c->plans.begin(), c->plans.end(), p), c->plans.end());
+    }
+    delete p;
 }
 
 int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_events* events,

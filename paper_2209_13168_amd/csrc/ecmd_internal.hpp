@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ecmd.h"
+
 namespace ecmd {
 
 typedef __int128 i128;
@@ -130,14 +132,27 @@ hipError_t launch_winparam(hipStream_t s, const Geometry& g, const float* tau, c
 // Counters of the prep (per window, tile, owned/guest and walk class).
 size_t prep_counters(int B, int T);
 // phase 0: count events per (window, tile, owned/guest, walk class) and scan
-// into segments; phase 1: scatter the events into their segments.
+// into segments; err_flag[w] is set when window w has an invalid event.
+// phase 1: scatter the events into their segments; with cap >= 0, seg_off
+// holds the scan of phase 0 and nothing is written when its total exceeds
+// cap records.  Blocks at or past blk_start[B] return at once, so nblk may
+// be any upper bound of blk_start[B].
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
                        const float* t_rel, const signed char* pol, const long long* offsets, const WinParam* wp, int B,
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
-                       unsigned long long* cursor, float4* ev, int* err_flag);
+                       unsigned long long* cursor, float4* ev, int* err_flag, long long cap);
+// Checks made on the device before the search (the asynchronous plan):
+// window w starts finished with status wstat[w] when that is non-zero,
+// ECMD_EINVAL when werr[w] (an invalid event), ECMD_ENOMEM when the binned
+// records exceed cap.  wstat == NULL: no checks.
+struct InitCheck {
+    const int* wstat;
+    const int* werr;
+    long long cap;
+};
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
-                       const long long* seg_off);
+                       const long long* seg_off, InitCheck chk);
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active);
@@ -191,6 +206,15 @@ hipError_t launch_seed_from_pred(hipStream_t s, const float* pred, int B, float 
 // as its binning range r_lo, r_hi
 hipError_t launch_live_range(hipStream_t s, const Search& sp, const WinState* st, const Node* front, const Sel* sel,
                              WinParam* wp, int B);
+
+// asynchronous plan: device-side window checks and prep block prefix (one
+// workgroup), a fill, and the per-window results
+hipError_t launch_plan_check(hipStream_t s, const long long* off, const float* tau, int B, float d_hi, int W, int H,
+                             long long max_events, int chunk, int* wstat, int* werr, int* blk, Queue* q,
+                             int* n_active);
+hipError_t launch_fill_u32(hipStream_t s, unsigned* p, long long n, unsigned v);
+hipError_t launch_plan_results(hipStream_t s, const Search& sp, int B, const WinState* st, const long long* off,
+                               const float* tau, ecmd_result* out);
 
 // calibration (roofline denominators measured on the device)
 hipError_t launch_lds_atomics(hipStream_t s, int blocks, int iters, unsigned* sink);

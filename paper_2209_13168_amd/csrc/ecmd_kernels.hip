@@ -194,6 +194,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, int* __restrict__ cnt, int* __restrict__ err_flag) {
     __shared__ int s_cnt[kCtr];
+    if ((int)blockIdx.x >= blk_start[B]) return;  // a grid sized for the largest batch
     const int nc = g.T * 2 * kNB;
     for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
     __syncthreads();
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     const WinParam p = wp[w];
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
-        if (!e.valid) atomicOr(err_flag, 1);
+        if (!e.valid) atomicOr(&err_flag[w], 1);
         if (!e.ok) continue;
         const int sb = seg_base(g, pol, i);
         for (int ty = e.ty0; ty <= e.ty1; ++ty)
@@ -257,9 +258,11 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     Geometry g, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ t_rel,
     const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, unsigned long long* __restrict__ cursor,
-    float4* __restrict__ ev) {
+    const long long* __restrict__ total, long long cap, float4* __restrict__ ev) {
     __shared__ int s_cnt[kCtr];
     __shared__ unsigned long long s_base[kCtr];
+    if ((int)blockIdx.x >= blk_start[B]) return;
+    if (total && *total > cap) return;  // the records would not fit the store: nothing is written
     const int nc = g.T * 2 * kNB;
     for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
     __syncthreads();
@@ -302,7 +305,7 @@ size_t prep_counters(int B, int T) { return (size_t)B * T * 2 * kNB; }
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
                        const float* t_rel, const signed char* pol, const long long* offsets, const WinParam* wp, int B,
                        const int* blk_start, int nblk, int chunk, int* cnt, long long* seg_off, int* seg_own,
-                       unsigned long long* cursor, float4* ev, int* err_flag) {
+                       unsigned long long* cursor, float4* ev, int* err_flag, long long cap) {
     if (phase == 0) {
         if (nblk > 0) {
             k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cnt,
@@ -315,7 +318,7 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
     }
     if (nblk > 0) {
         k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cursor,
-                                                     ev);
+                                                     cap >= 0 ? seg_off + (long long)B * g.T : nullptr, cap, ev);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -745,12 +748,25 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
                                               const float* __restrict__ seeds, int B, WinState* __restrict__ st,
                                               Sel* __restrict__ sel, Hyp* __restrict__ hyps, int* __restrict__ act,
                                               Item* __restrict__ items, int qcap, Queue* __restrict__ q, int T,
-                                              const long long* __restrict__ seg_off) {
+                                              const long long* __restrict__ seg_off, InitCheck chk) {
     const int w = blockIdx.x;
     const unsigned top = 1u << sp.L;
     Sel* sl = sel + (long long)w * sp.F;
     __shared__ int s_nsel, s_nt, s_wave[NWF];
     __shared__ int s_tiles[kMaxTiles];
+    if (chk.wstat) {
+        const int bad = chk.wstat[w] ? chk.wstat[w]
+                        : chk.werr[w] ? -1                                  // ECMD_EINVAL
+                        : seg_off[(long long)B * T] > chk.cap ? -2 : 0;     // ECMD_ENOMEM
+        if (bad) {
+            if (threadIdx.x == 0) {
+                WinState s = WinState{};
+                s.status = bad;
+                st[w] = s;
+            }
+            return;
+        }
+    }
     if (threadIdx.x == 0) {
         WinState s = WinState{};
         s.Kinc_hi = -1;
@@ -794,9 +810,9 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
 
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
-                       const long long* seg_off) {
+                       const long long* seg_off, InitCheck chk) {
     if (B <= 0) return hipSuccess;
-    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, act, items, qcap, q, T, seg_off);
+    k_init<<<B, NTF, 0, s>>>(sp, wp, seeds, B, st, sel, hyps, act, items, qcap, q, T, seg_off, chk);
     return hipGetLastError();
 }
 
@@ -913,6 +929,9 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s.event_hyp += s_nbound * p.n_events;
         s.pixel_updates += (long long)s_pix;
         s.nodes_pruned += s_pruned;
+        // the gap certified so far (queued and selected nodes), kept for a
+        // search that is cut short after this step
+        sp128(best_gap < 0 ? (i128)0 : best_gap, s.gap_hi, s.gap_lo);
         int stop = 0;
         if (overflow) {
             s.status = -5;  // ECMD_EFRONTIER
@@ -1063,6 +1082,163 @@ hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, 
     if (B <= 0) return hipSuccess;
     k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, act, part, items, qcap, q_fill,
                                 n_active);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ asynchronous plan
+
+// The host-side checks of a synchronous call, made on the device for the
+// launches of a plan: window w is valid when its offsets are non-negative and
+// non-decreasing, it holds fewer than 2^28 events, its exact sums fit 64
+// bits, tau > 0 is finite and d_hi * tau < 1 (eq. (11)).  n: its events.
+__device__ __forceinline__ bool window_ok(const long long* off, const float* tau, int w, float d_hi, int W, int H,
+                                          long long& n) {
+    const long long a = off[w], b = off[w + 1];
+    n = b - a;
+    if (a < 0 || n < 0 || n >= kMaxWindowEvents) return false;
+    const double bound = (double)n * (double)n * 2.0 * ((double)W + H + 3.0);
+    if (bound >= 9.0e18) return false;
+    const float t = tau[w];
+    if (!(t > 0.0f) || !isfinite(t)) return false;
+    return d_hi * t < 1.0f;
+}
+
+constexpr int kCheckThreads = 1024;
+
+// One workgroup: wstat[w] = 0 for a valid window, else ECMD_EINVAL (every
+// window when the valid ones hold more than max_events events); blk = the
+// exclusive prefix of the prep blocks (`chunk` events each) of the valid
+// windows, B + 1 entries; werr, both queue sets and n_active cleared.
+// Thread k checks the windows [k * per, (k + 1) * per).
+__global__ __launch_bounds__(kCheckThreads) void k_plan_check(
+    const long long* __restrict__ off, const float* __restrict__ tau, int B, float d_hi, int W, int H,
+    long long max_events, int chunk, int* __restrict__ wstat, int* __restrict__ werr, int* __restrict__ blk,
+    Queue* __restrict__ q, int* __restrict__ n_active) {
+    __shared__ long long s_ev[kCheckThreads / 64];
+    __shared__ int s_scan[kCheckThreads];
+    const int tid = threadIdx.x;
+    if (tid < 2 * kXcd) {
+        q[tid].n_items = 0;
+        q[tid].next = 0;
+    }
+    if (tid == 0) *n_active = 0;
+    const int per = (B + kCheckThreads - 1) / kCheckThreads;
+    const int w0 = min(B, tid * per), w1 = min(B, w0 + per);
+    long long ev = 0;
+    int nb = 0;
+    for (int w = w0; w < w1; ++w) {
+        long long n;
+        if (window_ok(off, tau, w, d_hi, W, H, n)) {
+            ev += n;
+            nb += (int)((n + chunk - 1) / chunk);
+        }
+    }
+    // events of the valid windows: wave sums, then the workgroup's
+    for (int o = 32; o > 0; o >>= 1) ev += __shfl_xor(ev, o);
+    if ((tid & 63) == 0) s_ev[tid >> 6] = ev;
+    // inclusive scan of the block counts (Hillis-Steele)
+    s_scan[tid] = nb;
+    __syncthreads();
+    for (int o = 1; o < kCheckThreads; o <<= 1) {
+        const int a = tid >= o ? s_scan[tid - o] : 0;
+        __syncthreads();
+        s_scan[tid] += a;
+        __syncthreads();
+    }
+    long long total = 0;
+    for (int k = 0; k < kCheckThreads / 64; ++k) total += s_ev[k];
+    const bool over = total > max_events;
+    int run = over ? 0 : s_scan[tid] - nb;
+    for (int w = w0; w < w1; ++w) {
+        long long n;
+        const bool ok = window_ok(off, tau, w, d_hi, W, H, n) && !over;
+        wstat[w] = ok ? 0 : -1;  // ECMD_EINVAL
+        werr[w] = 0;
+        blk[w] = run;
+        if (ok) run += (int)((n + chunk - 1) / chunk);
+    }
+    if (tid == kCheckThreads - 1) blk[B] = over ? 0 : s_scan[tid];
+}
+
+__global__ void k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// Correctly rounded conversion of a 128-bit integer to double: the top 64
+// significant bits, with a sticky bit for any below them, are converted
+// (one rounding) and scaled by a power of two (exact).
+__device__ __forceinline__ double i128_to_double(i128 v) {
+    const bool neg = v < 0;
+    const unsigned __int128 u = neg ? (unsigned __int128)0 - (unsigned __int128)v : (unsigned __int128)v;
+    const unsigned long long hi = (unsigned long long)(u >> 64);
+    double r;
+    if (hi == 0) {
+        r = (double)(unsigned long long)u;
+    } else {
+        const int sh = 64 - __clzll(hi);
+        unsigned long long top = (unsigned long long)(u >> sh);
+        top |= (u & ((((unsigned __int128)1) << sh) - 1)) != 0 ? 1ull : 0ull;
+        r = ldexp((double)top, sh);
+    }
+    return neg ? -r : r;
+}
+
+// Per-window results of a plan launch, written to `out` (device memory or
+// pinned host memory), with the same arithmetic as a synchronous call.
+__global__ void k_plan_results(Search sp, int B, const WinState* __restrict__ st, const long long* __restrict__ off,
+                               const float* __restrict__ tau, ecmd_result* __restrict__ out) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= B) return;
+    const WinState s = st[w];
+    ecmd_result r = {};
+    r.L = (uint32_t)sp.L;
+    if (s.status == -1 || s.status == -2) {  // rejected before the search: only the status
+        r.status = s.status;
+        out[w] = r;
+        return;
+    }
+    r.status = s.active ? -4 : s.status;  // still running when the steps ran out: ECMD_EBUDGET
+    r.j_star = s.j_inc;
+    r.d_hat = grid_d(sp.d_lo, sp.d_hi, sp.L, s.j_inc);
+    r.K_lo = s.Kinc_lo;
+    r.K_hi = s.Kinc_hi;
+    const double M2 = (double)sp.M * (double)sp.M;
+    r.contrast = i128_to_double(mk128(s.Kinc_hi, s.Kinc_lo)) / M2;
+    const double t = (double)tau[w];
+    r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * t);
+    r.gap = s.status == -5 ? (double)INFINITY : i128_to_double(mk128(s.gap_hi, s.gap_lo)) / M2;
+    r.n_events = off[w + 1] - off[w];
+    r.nodes_expanded = s.nodes_expanded;
+    r.nodes_pruned = s.nodes_pruned;
+    r.point_evals = s.point_evals;
+    r.bound_evals = s.bound_evals;
+    r.event_hyp_evals = s.event_hyp;
+    r.pixel_updates = s.pixel_updates;
+    r.steps = s.steps;
+    r.seeded = s.seeded;
+    out[w] = r;
+}
+
+hipError_t launch_plan_check(hipStream_t s, const long long* off, const float* tau, int B, float d_hi, int W, int H,
+                             long long max_events, int chunk, int* wstat, int* werr, int* blk, Queue* q,
+                             int* n_active) {
+    k_plan_check<<<1, kCheckThreads, 0, s>>>(off, tau, B, d_hi, W, H, max_events, chunk, wstat, werr, blk, q,
+                                             n_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t s, unsigned* p, long long n, unsigned v) {
+    if (n <= 0) return hipSuccess;
+    const long long nb = (n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192;
+    k_fill_u32<<<(int)nb, 256, 0, s>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_results(hipStream_t s, const Search& sp, int B, const WinState* st, const long long* off,
+                               const float* tau, ecmd_result* out) {
+    if (B <= 0) return hipSuccess;
+    k_plan_results<<<(B + 255) / 256, 256, 0, s>>>(sp, B, st, off, tau, out);
     return hipGetLastError();
 }
 

@@ -65,6 +65,11 @@ class PlanInfo(C.Structure):
                 ("rowcut", C.c_int32 * 65)]
 
 
+class PlanLimitsS(C.Structure):
+    _fields_ = [("max_windows", C.c_int32), ("max_steps", C.c_int32), ("max_events", C.c_int64),
+                ("max_records", C.c_int64), ("polarity", C.c_int32), ("reserved", C.c_int32)]
+
+
 class TuningS(C.Structure):
     _fields_ = [("frontier_batch", C.c_int32), ("tile_px", C.c_int32), ("graph", C.c_int32),
                 ("group", C.c_int32)]
@@ -128,6 +133,10 @@ def _load():
         "ecmd_ctx_set_profiling": ([vp, C.c_int], C.c_int),
         "ecmd_plan": ([C.POINTER(Sensor), C.POINTER(SearchS), i32, i64, i32, C.POINTER(PlanInfo)], C.c_int),
         "ecmd_grid_point": ([f32, f32, u32, u32], f32),
+        "ecmd_plan_create": ([vp, C.POINTER(Sensor), C.POINTER(SearchS), C.POINTER(PlanLimitsS), C.POINTER(vp)],
+                             C.c_int),
+        "ecmd_plan_launch": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], C.c_int),
+        "ecmd_plan_destroy": ([vp], None),
         "ecmd_measure_peaks": ([vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_set_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_ctx_get_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
@@ -376,6 +385,14 @@ class Context:
         self._check(rc, allow=(EBUDGET, EFRONTIER))
         return [Result.of(out[i]) for i in range(B)]
 
+    def batch_plan(self, sensor: Sensor, d_lo: float, d_hi: float, eps: float, max_windows: int, max_events: int,
+                   gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0, frontier_capacity: int = 0,
+                   max_steps: int = 0, max_records: int = 0, polarity: bool = False) -> "BatchPlan":
+        """Device buffers for asynchronous batched searches up to the limits."""
+        return BatchPlan(self, sensor, _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity),
+                         PlanLimitsS(int(max_windows), int(max_steps), int(max_events), int(max_records),
+                                     1 if polarity else 0, 0))
+
     # -------------------------------------------------------------- probes
     def probe_pixels(self, sensor: Sensor, x, y, t_rel, tau: float, d: float, out=None):
         a = _Args()
@@ -488,6 +505,64 @@ class Context:
         out = _empty_like(x, B * GRID * GRID, np.uint16)
         self._check(lib().ecmd_downsample(self.h, C.byref(sensor), px, py, po, B, a.flags, a.ptr(out, np.uint16)))
         return out
+
+
+class BatchPlan:
+    """An asynchronous batched search (``ecmd_plan_*``): ``launch`` only
+    enqueues kernels on the context's stream and writes ``ecmd_result``
+    records into a caller buffer (see ``result_buffer``), so it can be
+    captured into a graph."""
+
+    def __init__(self, ctx: Context, sensor: Sensor, search: SearchS, limits: PlanLimitsS):
+        self.ctx = ctx
+        h = C.c_void_p()
+        rc = lib().ecmd_plan_create(ctx.h, C.byref(sensor), C.byref(search), C.byref(limits), C.byref(h))
+        ctx._check(rc)
+        self.h = h
+        self.limits = {f: getattr(limits, f) for f, _ in PlanLimitsS._fields_ if f != "reserved"}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ecmd_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def result_buffer(B: int, device: bool = True):
+        """A torch byte buffer for B results: on the GPU, or pinned host memory."""
+        import torch
+
+        n = C.sizeof(ResultS) * max(int(B), 1)
+        if device:
+            return torch.zeros(n, dtype=torch.uint8, device="cuda")
+        return torch.zeros(n, dtype=torch.uint8, pin_memory=True)
+
+    def launch(self, x, y, t_rel, offsets, tau, out, d_seeds=None, polarity=None):
+        """Enqueue the search of len(tau) windows (torch CUDA tensors); the
+        results land in ``out`` when the stream reaches them."""
+        a = _Args()
+        B = int(tau.shape[0])
+        args = [a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32),
+                a.ptr(polarity, np.int8) if polarity is not None else None, a.ptr(offsets, np.int64),
+                a.ptr(tau, np.float32), B, a.ptr(d_seeds, np.float32) if d_seeds is not None else None]
+        if not a.device:
+            raise TypeError("plan launches take device arrays")
+        if out.numel() < C.sizeof(ResultS) * B:
+            raise ValueError("result buffer too small")
+        rc = lib().ecmd_plan_launch(self.h, *args, C.c_void_p(out.data_ptr()))
+        self.ctx._check(rc)
+
+    @staticmethod
+    def results(out, B: int) -> list:
+        """Decode B results from a result buffer (after the stream reached them)."""
+        raw = out.detach().cpu().numpy().tobytes()
+        arr = (ResultS * B).from_buffer_copy(raw[:C.sizeof(ResultS) * B])
+        return [Result.of(arr[i]) for i in range(B)]
 
 
 class Cnn:

@@ -40,7 +40,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     from paper_2209_13168_amd import ecmd
 
     pairs = [("ecmd_sensor", ecmd.Sensor), ("ecmd_events", ecmd.EventsS), ("ecmd_window", ecmd.WindowS),
-             ("ecmd_plan_info", ecmd.PlanInfo),
+             ("ecmd_plan_info", ecmd.PlanInfo), ("ecmd_plan_limits", ecmd.PlanLimitsS),
              ("ecmd_search", ecmd.SearchS), ("ecmd_result", ecmd.ResultS), ("ecmd_profile", ecmd.ProfileS),
              ("ecmd_tuning", ecmd.TuningS)]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ecmd.h"', "int main(void) {"]

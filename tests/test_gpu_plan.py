@@ -1,0 +1,262 @@
+"""The asynchronous batched search (``ecmd_plan_create`` / ``ecmd_plan_launch``):
+every launch only enqueues kernels, with the window checks made on the device.
+
+Its results must equal the synchronous batched call's field for field (the
+same search on the same device), and the canonical optimum of the oracle;
+per-window statuses cover the checks the synchronous call makes on the host;
+a launch captured into a graph gives the eager launch's results on every
+replay, with other work on the stream in between."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import config_windows, pack_batch
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("status", "j_star", "L", "d_hat", "K", "contrast", "d_end", "gap", "n_events", "nodes_expanded",
+          "nodes_pruned", "point_evals", "bound_evals", "event_hyp_evals", "pixel_updates", "steps", "seeded")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    assert torch.cuda.is_available()
+    c = ecmd.Context(0)
+    yield c
+    c.close()
+
+
+def _sensor(spec):
+    from paper_2209_13168_amd import ecmd
+
+    return ecmd.sensor(spec.width, spec.height, spec.foe)
+
+
+def _dev(*arrs):
+    import torch
+
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+
+
+def _mixed_windows(cfg="c2", ns=(0, 1, 500, 3000, 9000, 20_000)):
+    from synth.ventral import make_window
+
+    ws = config_windows(cfg, range(len(ns)))
+    return [make_window(dataclasses.replace(w.spec, n_events=n), 2, 300 + i) for i, (w, n) in enumerate(zip(ws, ns))]
+
+
+def _launch(plan, x, y, t, off, tau, seeds=None, pol=None, device_out=True):
+    import torch
+
+    B = int(tau.shape[0])
+    out = plan.result_buffer(B, device=device_out)
+    plan.launch(x, y, t, off, tau, out, d_seeds=seeds, polarity=pol)
+    torch.cuda.synchronize()
+    return plan.results(out, B)
+
+
+def _same(a, b, fields=FIELDS):
+    for f in fields:
+        assert getattr(a, f) == getattr(b, f), (f, a, b)
+
+
+def test_plan_equals_the_synchronous_call_and_the_oracle(ctx, orc):
+    wins = _mixed_windows()
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=8, max_events=int(off[-1]) + 100)
+    assert plan.limits["max_steps"] == 256 and plan.limits["max_records"] >= int(off[-1])
+    got = _launch(plan, *_dev(x, y, t, off, tau))
+    for i, w in enumerate(wins):
+        _same(got[i], sync[i])
+        o = orc.bnb(orc.Events.of_window(w), s.d_lo, s.d_hi, 1e-4)
+        assert (got[i].status, got[i].j_star, got[i].K) == (0, o.j_star, o.K), (i, got[i], o)
+    # a second launch on the same plan with fewer windows, results in pinned host memory
+    got2 = _launch(plan, *_dev(*pack_batch(wins[3:])), device_out=False)
+    for i in range(3):
+        _same(got2[i], sync[3 + i])
+    plan.close()
+
+
+def test_plan_on_guest_tiles_with_rebinning(ctx):
+    """640x480 windows: quadrants split into tiles, guest copies, the four
+    re-binnings of the launch."""
+    wins = config_windows("c3", range(4), n_events=40_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, s.eps, max_windows=4, max_events=int(off[-1]))
+    got = _launch(plan, *_dev(x, y, t, off, tau))
+    for a, b in zip(got, sync):
+        _same(a, b)
+    plan.close()
+
+
+def test_plan_seeds_and_polarity(ctx):
+    wins = config_windows("c2", range(4), n_events=12_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    seeds = np.array([w.spec.d_true for w in wins], np.float32)
+    seeds[1] = np.nan
+    sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4, d_seeds=seeds)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=4, max_events=int(off[-1]))
+    got = _launch(plan, *_dev(x, y, t, off, tau), seeds=_dev(seeds)[0])
+    for a, b in zip(got, sync):
+        _same(a, b)
+    assert [r.seeded for r in got] == [1, 0, 1, 1]
+    plan.close()
+
+    p = np.concatenate([w.p for w in wins]).astype(np.int8)
+    sync_p = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4, polarity=p)
+    plan_p = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=4, max_events=int(off[-1]),
+                            polarity=True)
+    got_p = _launch(plan_p, *_dev(x, y, t, off, tau), pol=_dev(p)[0])
+    for a, b in zip(got_p, sync_p):
+        _same(a, b)
+    from paper_2209_13168_amd import ecmd
+
+    with pytest.raises(ecmd.EcmdError):  # polarity plan without polarities
+        _launch(plan_p, *_dev(x, y, t, off, tau))
+    plan_p.close()
+
+
+def test_plan_per_window_statuses(ctx):
+    """The synchronous call's host checks, per window on the device."""
+    from paper_2209_13168_amd import ecmd
+
+    wins = config_windows("c2", range(5), n_events=4_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=5, max_events=int(off[-1]) + 1)
+    bad_tau = tau.copy()
+    bad_tau[1] = 0.0          # tau must be > 0
+    bad_tau[3] = 1.0 / s.d_hi  # d_hi * tau >= 1
+    xb = x.copy()
+    xb[off[2] + 7] = np.nan    # a non-finite event in window 2
+    got = _launch(plan, *_dev(xb, y, t, off, bad_tau))
+    assert [r.status for r in got] == [0, ecmd.EINVAL, ecmd.EINVAL, ecmd.EINVAL, 0]
+    for i in (0, 4):
+        _same(got[i], sync[i])
+    for i in (1, 2, 3):
+        assert (got[i].K, got[i].nodes_expanded, got[i].n_events) == (0, 0, 0)
+    # offsets that decrease reject that window only (window 2 then starts
+    # one event before window 1 ends: a valid window one event larger, which
+    # the plan's max_events still holds)
+    off_bad = off.copy()
+    off_bad[2] = off[1] - 1
+    got = _launch(plan, *_dev(x, y, t, off_bad, tau))
+    assert [r.status for r in got] == [0, ecmd.EINVAL, 0, 0, 0]
+    assert got[2].n_events == off[3] - off[1] + 1
+    for i in (0, 3, 4):
+        _same(got[i], sync[i])
+    plan.close()
+    # more events than the plan holds: every window
+    small = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=5, max_events=int(off[-1]) - 1)
+    assert all(r.status == ecmd.EINVAL for r in _launch(small, *_dev(x, y, t, off, tau)))
+    small.close()
+    # fewer binned records than the events need: every window, nothing written
+    tight = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=5, max_events=int(off[-1]),
+                           max_records=int(off[-1]) // 2)
+    assert all(r.status == ecmd.ENOMEM for r in _launch(tight, *_dev(x, y, t, off, tau)))
+    tight.close()
+    # call-level errors
+    with pytest.raises(ecmd.EcmdError):
+        ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=0, max_events=10)
+    p2 = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=2, max_events=int(off[-1]))
+    with pytest.raises(ecmd.EcmdError):  # B above max_windows
+        _launch(p2, *_dev(x, y, t, off, tau))
+    p2.close()
+
+
+def test_plan_step_limit_certifies_its_gap(ctx):
+    """Stopped after 4 steps: ECMD_EBUDGET with the incumbent and a gap that
+    bounds the distance to the optimum (eq. (15)'s bound over the queue)."""
+    from paper_2209_13168_amd import ecmd
+
+    wins = config_windows("c2", range(3), n_events=20_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    full = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, s.eps, max_windows=3, max_events=int(off[-1]), max_steps=4)
+    assert plan.limits["max_steps"] == 4
+    got = _launch(plan, *_dev(x, y, t, off, tau))
+    M2 = float(s.width * s.height) ** 2
+    for a, b in zip(got, full):
+        assert a.status == ecmd.EBUDGET and a.steps == 4
+        assert a.K <= b.K
+        assert a.gap > 0 and (b.K - a.K) / M2 <= a.gap * (1 + 1e-12)
+    plan.close()
+
+
+def test_plan_graph_replays(ctx):
+    """A captured launch replayed three times, with a synchronous batched call
+    and a different eager launch between replays: every replay gives the
+    eager results."""
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    wins = _mixed_windows(ns=(2000, 0, 7000, 15_000))
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    stream = torch.cuda.Stream()
+    gctx = ecmd.Context(0, stream=stream.cuda_stream)
+    plan = gctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=4, max_events=int(off[-1]))
+    dx, dy, dt, doff, dtau = _dev(x, y, t, off, tau)
+    torch.cuda.synchronize()
+    eager = plan.result_buffer(4)
+    with torch.cuda.stream(stream):
+        plan.launch(dx, dy, dt, doff, dtau, eager)
+    torch.cuda.synchronize()
+    ref = plan.results(eager, 4)
+    other = _dev(*pack_batch(wins[2:]))
+    out = plan.result_buffer(4)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        plan.launch(dx, dy, dt, doff, dtau, out)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = plan.results(out, 4)
+        for a, b in zip(got, ref):
+            _same(a, b)
+        # other work on the same buffers and stream between replays
+        scratch = plan.result_buffer(2)
+        with torch.cuda.stream(stream):
+            plan.launch(*other, scratch)
+        torch.cuda.synchronize()
+        sync = gctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+        for a, b in zip(sync, ref):
+            _same(a, b)
+    del g
+    plan.close()
+    gctx.close()
+
+
+def test_plan_outlives_its_context_as_an_empty_handle():
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    c = ecmd.Context(0)
+    w = config_windows("c1", [0])[0]
+    s = w.spec
+    plan = c.batch_plan(_sensor(s), s.d_lo, s.d_hi, s.eps, max_windows=1, max_events=w.n)
+    c.close()
+    x, y, t, off, tau = _dev(*pack_batch([w]))
+    out = plan.result_buffer(1)
+    rc = ecmd.lib().ecmd_plan_launch(plan.h, x.data_ptr(), y.data_ptr(), t.data_ptr(), None, off.data_ptr(),
+                                     tau.data_ptr(), 1, None, out.data_ptr())
+    assert rc == ecmd.EINVAL
+    plan.close()
+    torch.cuda.synchronize()
