@@ -163,9 +163,10 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
 
 /* Launch tuning of a context, used by every search call whose
  * ecmd_search.frontier_batch is 0.  frontier_batch: nodes expanded together
- * per window and step (0 = 64).  tile_px: largest image tile per LDS
- * histogram (0 = what the LDS holds; smaller values split the FOE quadrants
- * further, trading guest copies for occupancy).  graph: replay the step
+ * per window and step (0 = 64).  tile_px: most LDS counters per image
+ * tile, (w + 2)(h + 2) for a w x h tile with its one-pixel border (0 = what
+ * the LDS holds; smaller values split the FOE quadrants further, trading
+ * guest copies for occupancy).  graph: replay the step
  * loop as a captured hipGraph (0 = plain launches).  group: hypotheses of
  * one window and tile evaluated per work item (0 = chosen from the batch
  * size: 1 while there are fewer than ~48 items per CU, else 2). */
@@ -192,7 +193,7 @@ typedef struct {
     int32_t segments;        /* event segments per window: tiles x images */
     int32_t ntx, nty;        /* tile grid */
     int32_t max_tile_px;     /* largest tile (pixels) */
-    int32_t tile_budget_px;  /* the size limit the plan met */
+    int32_t tile_budget_px;  /* the limit the plan met on (w + 2)(h + 2) of the largest tile */
     int32_t colcut[65];      /* column band edges, ntx + 1 used */
     int32_t rowcut[65];      /* row band edges, nty + 1 used */
 } ecmd_plan_info;

@@ -212,7 +212,8 @@ static int grid_depth(float d_lo, float d_hi, float eps) {
 
 // Tile plan: column and row cuts at the FOE lines when the FOE is an
 // integer point strictly inside the sensor (no event crosses them), then
-// each band split evenly until every tile fits the LDS budget.
+// each band split evenly until every tile's counters, (w + 2)(h + 2) with
+// the one-cell border, fit the budget max_px.
 // npol = 1, or 2 for the polarity-aware contrast (one tiled image per
 // polarity); segments = tiles x npol stay within kMaxTiles.
 static bool plan_geometry(int W, int H, float cx, float cy, int max_px, int npol, Geometry& g) {
@@ -247,7 +248,8 @@ static bool plan_geometry(int W, int H, float cx, float cy, int max_px, int npol
             std::vector<int> c = split(bx, kx), r = split(by, ky);
             int ntx = (int)c.size() - 1, nty = (int)r.size() - 1;
             if (ntx * nty * npol > kMaxTiles) continue;
-            if ((long long)max_band(c) * max_band(r) > max_px) continue;
+            // counters of the largest tile, with its one-cell border
+            if ((long long)(max_band(c) + 2) * (max_band(r) + 2) > max_px) continue;
             // fewest tiles, then the squarest
             int score = ntx * nty * 1000 + std::abs(max_band(c) - max_band(r)) % 1000;
             if (best < 0 || score < best) {
@@ -265,6 +267,7 @@ static bool plan_geometry(int W, int H, float cx, float cy, int max_px, int npol
     for (int i = 0; i <= g.ntx; ++i) g.colcut[i] = bc[i];
     for (int i = 0; i <= g.nty; ++i) g.rowcut[i] = br[i];
     g.max_tile_px = max_band(bc) * max_band(br);
+    g.ring_px = (max_band(bc) + 2) * (max_band(br) + 2);
     return true;
 }
 
@@ -371,9 +374,10 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     return ECMD_OK;
 }
 
-// Largest tile (pixels) whose evaluation workgroup fits the LDS.
+// Most counters (a tile's pixels and its one-cell border) that the
+// evaluation workgroup's LDS holds.
 static int tile_budget_for(size_t max_lds) {
-    int px = (int)(max_lds / 4) - kEvalThreads - 64;
+    int px = (int)(max_lds / 4);
     while (px > 0 && eval_lds_bytes(px) > max_lds) --px;
     return px;
 }
@@ -459,7 +463,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     HIPCHK(c, launch_init(c->stream, sp, c->wp.as<WinParam>(), in.seeds, B, c->state.as<WinState>(),
                           c->sel.as<Sel>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(), qcap, &q[0],
                           T, c->seg_off.as<long long>(), InitCheck{nullptr, nullptr, 0}));
-    const size_t lds = eval_lds_bytes(g.max_tile_px);
+    const size_t lds = eval_lds_bytes(g.ring_px);
     int nb = 0;
     HIPCHK(c, eval_setup(c, lds, &nb));
     int* h_active = (int*)c->pinned.p;
@@ -997,7 +1001,7 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     get(p->queues, sizeof(Queue) * 2 * kXcd);
     get(p->part, sizeof(Part) * (size_t)Bm * sp.HS * T);
     get(p->n_active, sizeof(int));
-    p->lds = eval_lds_bytes(g.max_tile_px);
+    p->lds = eval_lds_bytes(g.ring_px);
     if (e == hipSuccess) e = eval_setup(c, p->lds, &p->nb);
     if (e != hipSuccess) {
         plan_release(p);
@@ -1277,7 +1281,7 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
             dimg = c->img.as<unsigned>();
         }
     }
-    const size_t lds = eval_lds_bytes(g.max_tile_px);
+    const size_t lds = eval_lds_bytes(g.ring_px);
     int nb = 0;
     HIPCHK(c, eval_setup(c, lds, &nb));
     Queue* q = c->queues.as<Queue>();

@@ -62,6 +62,7 @@ struct Geometry {
     int colcut[kMaxTiles + 1];    // column band edges (ntx + 1)
     int rowcut[kMaxTiles + 1];    // row band edges (nty + 1)
     int max_tile_px;              // largest tile area (pixels)
+    int ring_px;                  // largest tile's counters with their one-cell border, (w + 2)(h + 2)
 };
 
 struct WinParam {
@@ -169,8 +170,9 @@ hipError_t launch_downsample(hipStream_t s, const float* x, const float* y, cons
                              int B, int W, int H, const int* blk_start, int nblk, int chunk,
                              unsigned* counts, uint16_t* out);
 hipError_t eval_set_lds(size_t bytes);
-// LDS bytes of the evaluation kernel for tiles of up to max_tile_px pixels.
-size_t eval_lds_bytes(int max_tile_px);
+// LDS bytes of the evaluation kernel for tiles of up to ring_px counters
+// (a tile of w x h pixels has (w + 2)(h + 2), its one-cell border included).
+size_t eval_lds_bytes(int ring_px);
 hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes);
 // Events with t in [t0, t1], compacted in order, t_rel = float(t - t0);
 // their polarities too when p is not NULL.

@@ -334,25 +334,62 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // edges; within 2^-8 px of the corner both side pixels are counted.
 // Each increment returns the previous count; it is added to `sumold` one
 // increment later (`pend`), so the wait for it overlaps the next step.
-// Pixels outside the tile go to the thread's private spill word `spill`.
+// Pixels outside the tile are clamped onto its one-cell border (`Ring`),
+// whose counts are removed at the end.
 struct WalkAcc {
     unsigned long long sumold;
     unsigned pend;
     unsigned visits;  // walk increments (the start pixels are counted by the caller)
 };
 
-__device__ __forceinline__ void tile_add(unsigned* __restrict__ tile, unsigned spill, int x0, int y0, unsigned tw,
-                                         unsigned th, int px, int py, WalkAcc& acc) {
-    const unsigned lx = (unsigned)(px - x0), ly = (unsigned)(py - y0);
-    const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
-    const unsigned old = atomicAdd(&tile[a], 1u);
+// The tile's counters in LDS with a one-cell border: pixel (kx, ky), clamped
+// to [xlo, xhi] x [ylo, yhi] = [x0 - 1, x0 + tw] x [y0 - 1, y0 + th], is
+// counter ky * rw + kx + base, rw = tw + 2.  Border counters collect every
+// increment outside the tile (other tiles, outside the image).  `org` is
+// the counter array shifted by base (org[ky * rw + kx] is pixel (kx, ky)),
+// so an address is one 24-bit mad and one shift-add.
+struct Ring {
+    int xlo, xhi, ylo, yhi;
+    int rw, base;
+    int vxhi, vyhi;  // xhi, yhi held in vector registers (the clamp takes one scalar operand)
+};
+
+// v copied into a vector register that the compiler keeps (rather than
+// copying it again before every use)
+__device__ __forceinline__ int to_vgpr(int v) {
+    int r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+    return r;
+}
+
+// a * b + c for 24-bit signed a, b in one instruction, b uniform (left to
+// itself the compiler scales both terms of the index separately)
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
+// v clamped to [lo, hi] (lo <= hi, lo uniform) in one instruction
+__device__ __forceinline__ int clampi(int v, int lo, int hi) {
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(v), "s"(lo), "v"(hi));
+    return r;
+}
+
+__device__ __forceinline__ unsigned* ring_at(unsigned* org, const Ring& R, int kx, int ky) {
+    return org + mad24(ky, R.rw, kx);
+}
+
+__device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py, WalkAcc& acc) {
+    const int cx = clampi(px, R.xlo, R.vxhi), cy = clampi(py, R.ylo, R.vyhi);
+    const unsigned old = atomicAdd(ring_at(org, R, cx, cy), 1u);
     acc.sumold += acc.pend;
     acc.pend = old;
 }
 
-__device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned spill, int x0, int y0,
-                                          unsigned tw, unsigned th, int kx, int ky, int kxb, int kyb,
-                                          float xf, float yf, float axf, float ayf, WalkAcc& acc) {
+__device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, int ky, int kxb,
+                                          int kyb, float xf, float yf, float axf, float ayf, WalkAcc& acc) {
     const int sx = (kxb > kx) - (kxb < kx);
     const int sy = (kyb > ky) - (kyb < ky);
     const double x = (double)xf, y = (double)yf;
@@ -366,30 +403,27 @@ __device__ __forceinline__ void walk_tile(unsigned* __restrict__ tile, unsigned 
         const double e = ex - ey;
         const bool lo = e < -thr, hi = e > thr;
         if (dx && dy && !lo && !hi) {  // the ray passes near the corner: both side pixels
-            tile_add(tile, spill, x0, y0, tw, th, kx + sx, ky, acc);
-            tile_add(tile, spill, x0, y0, tw, th, kx, ky + sy, acc);
+            tile_add(org, R, kx + sx, ky, acc);
+            tile_add(org, R, kx, ky + sy, acc);
             acc.visits += 2;
         }
         kx += (dx && (!dy || !hi)) ? sx : 0;
         ky += (dy && (!dx || !lo)) ? sy : 0;
-        tile_add(tile, spill, x0, y0, tw, th, kx, ky, acc);
+        tile_add(org, R, kx, ky, acc);
         acc.visits += 1;
     } while (kx != kxb || ky != kyb);
 }
 
-// LDS layout of k_eval: [tile: tw*th counters][spill: one word per thread]
+// LDS layout of k_eval: [tile with its border: (tw + 2)(th + 2) counters]
 // (region rounded up to 16 bytes)[reduction scratch][work item].
 constexpr int kEvalWaves = kEvalThreads / 64;
 
-// Counter words of the LDS tile region (tile + one spill word per thread),
-// rounded up to whole 16-byte units so the clear can use 16-byte stores.
-__host__ __device__ __forceinline__ int eval_counter_words(int max_tile_px) {
-    return (max_tile_px + kEvalThreads + 3) & ~3;
-}
+// Counter words of the LDS tile region for tiles of up to ring_px counters
+// (border included), rounded up to whole 16-byte units so the clear can use
+// 16-byte stores.
+__host__ __device__ __forceinline__ int eval_counter_words(int ring_px) { return (ring_px + 3) & ~3; }
 
-size_t eval_lds_bytes(int max_tile_px) {
-    return (size_t)eval_counter_words(max_tile_px) * 4 + 3 * kEvalWaves * 8 + 16;
-}
+size_t eval_lds_bytes(int ring_px) { return (size_t)eval_counter_words(ring_px) * 4 + 3 * kEvalWaves * 8 + 16; }
 
 // Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
 // items from the queue until it is empty.  For each item it clears its LDS
@@ -405,7 +439,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     const int tid = threadIdx.x;
     unsigned* const tile = smem;
     unsigned long long* const s_red =
-        reinterpret_cast<unsigned long long*>(smem + eval_counter_words(g.max_tile_px));
+        reinterpret_cast<unsigned long long*>(smem + eval_counter_words(g.ring_px));
     int* const s_item = reinterpret_cast<int*>(s_red + 3 * kEvalWaves);
     if (blockIdx.x == 0 && tid < kXcd && q_reset) {
         q_reset[tid].n_items = 0;
@@ -441,9 +475,20 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const int ts = t % g.nsp;  // spatial tile of the segment
         const int tx = ts % g.ntx, ty = ts / g.ntx;
         const int x0 = g.colcut[tx], y0 = g.rowcut[ty];
-        const unsigned tw = (unsigned)(g.colcut[tx + 1] - x0), th = (unsigned)(g.rowcut[ty + 1] - y0);
-        const int npx = (int)(tw * th);
-        const unsigned spill = (unsigned)npx + (unsigned)tid;  // this thread's private word
+        const int tw = g.colcut[tx + 1] - x0, th = g.rowcut[ty + 1] - y0;
+        Ring R;
+        R.xlo = x0 - 1;
+        R.xhi = x0 + tw;
+        R.ylo = y0 - 1;
+        R.yhi = y0 + th;
+        R.rw = tw + 2;
+        R.base = -(R.ylo * R.rw + R.xlo);
+        R.vxhi = to_vgpr(R.xhi);
+        R.vyhi = to_vgpr(R.yhi);
+        unsigned* const org = tile + R.base;   // org[ky * rw + kx]: pixel (kx, ky)
+        const int ncnt = R.rw * (th + 2);       // counters, border included
+        const int nring = 2 * R.rw + 2 * th;    // border counters
+        const float fxlo = (float)R.xlo, fxhi = (float)R.xhi, fylo = (float)R.ylo, fyhi = (float)R.yhi;
         const long long seg = (long long)w * g.T + t;
         const long long beg = seg_off[seg], end = seg_off[seg + 1];
         const long long own_end = beg + seg_own[seg];
@@ -451,9 +496,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const int wh = w * HS + act[w * HS + item.r0 + gk];
         const Hyp hp = hyps[wh];
 
-        {  // clear the tile and the spill words, 16 bytes per store
+        {  // clear the counters, 16 bytes per store
             uint4* const t4 = reinterpret_cast<uint4*>(tile);
-            const int n4 = (npx + kEvalThreads + 3) >> 2;
+            const int n4 = (ncnt + 3) >> 2;
             for (int i = tid; i < n4; i += kEvalThreads) t4[i] = make_uint4(0u, 0u, 0u, 0u);
         }
         __syncthreads();
@@ -477,25 +522,24 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 float4 e[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) e[k] = at(i + k * S);
-                unsigned a[U];
+                int a[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
-                    const unsigned lx = (unsigned)(cvt_flr(fmaf(e[k].z, r, e[k].x)) - x0);
-                    const unsigned ly = (unsigned)(cvt_flr(fmaf(e[k].w, r, e[k].y)) - y0);
-                    a[k] = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
+                    const int kx = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e[k].z, r, e[k].x), fxlo, fxhi));
+                    const int ky = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e[k].w, r, e[k].y), fylo, fyhi));
+                    a[k] = mad24(ky, R.rw, kx);
                 }
                 unsigned old[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) old[k] = atomicAdd(&tile[a[k]], 1u);
+                for (int k = 0; k < U; ++k) old[k] = atomicAdd(org + a[k], 1u);
 #pragma unroll
                 for (int k = 0; k < U; ++k) sumold += old[k];
             }
             for (; i < nseg; i += S) {
                 const float4 e = at(i);
-                const unsigned lx = (unsigned)(cvt_flr(fmaf(e.z, r, e.x)) - x0);
-                const unsigned ly = (unsigned)(cvt_flr(fmaf(e.w, r, e.y)) - y0);
-                const unsigned a = (lx < tw && ly < th) ? __umul24(ly, tw) + lx : spill;
-                sumold += atomicAdd(&tile[a], 1u);
+                const int kx = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e.z, r, e.x), fxlo, fxhi));
+                const int ky = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e.w, r, e.y), fylo, fyhi));
+                sumold += atomicAdd(ring_at(org, R, kx, ky), 1u);
             }
         } else {
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
@@ -509,9 +553,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
                 nlow32 += (unsigned)(i < nown) & (unsigned)(max((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
                           (unsigned)(max((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
-                tile_add(tile, spill, x0, y0, tw, th, kxa, kya, acc);
-                if (kxa != kxb || kya != kyb)
-                    walk_tile(tile, spill, x0, y0, tw, th, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
+                tile_add(org, R, kxa, kya, acc);
+                if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
             };
             unsigned i = tid;
             if (i < nseg) {
@@ -531,11 +574,21 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             visits += acc.visits;
             nlow = nlow32;
         }
-        // Remove the spill word, whose m increments returned 0, 1, .., m-1;
-        // then the sum of squares is sum(2*old + 1) over the in-tile increments.
-        const unsigned m = tile[spill];
-        sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
-        unsigned long long hits = (unsigned long long)(visits - m);
+        // Remove the border counters: a counter's m increments returned 0, 1,
+        // .., m-1; then the sum of squares is sum(2*old + 1) over the in-tile
+        // increments.  Each thread takes some border counters (its own sums
+        // may wrap; the workgroup's totals are exact).
+        __syncthreads();
+        unsigned long long hits = visits;
+        for (int k = tid; k < nring; k += kEvalThreads) {
+            int idx;
+            if (k < R.rw) idx = k;                                      // top row
+            else if (k < 2 * R.rw) idx = (th + 1) * R.rw + (k - R.rw);  // bottom row
+            else idx = (1 + ((k - 2 * R.rw) >> 1)) * R.rw + (((k - 2 * R.rw) & 1) ? R.rw - 1 : 0);
+            const unsigned m = tile[idx];
+            sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
+            hits -= m;
+        }
         unsigned long long sq = 2ull * sumold + hits;
         // block reduction of (S, hits, nlow)
         sq = wave_total(sq);
@@ -565,9 +618,9 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
             const long long M = (long long)g.W * g.H;
             unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
-            for (int k = tid; k < npx; k += kEvalThreads) {
-                int lx = k % (int)tw, ly = k / (int)tw;
-                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[k];
+            for (int k = tid; k < tw * th; k += kEvalThreads) {
+                const int lx = k % tw, ly = k / tw;
+                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
             }
         }
         __syncthreads();  // the tile is cleared again for the next hypothesis

@@ -51,8 +51,12 @@ def test_tile_plan_invariants(W, H, foe, pol, tile_px):
     try:
         p = ecmd.plan(sen, 0.0, 1.5, 1e-5, polarity=pol, tile_px=tile_px)
     except ecmd.EcmdError:
-        # only a sensor that needs more tiles than the kernel holds may fail
-        assert W * H > 64 * 5000 // (2 if pol else 1) or W * H > 30_000 * 32
+        # only a sensor that needs more tiles than the kernel holds may fail:
+        # with at most 64 segments some tile has area A >= W*H/tiles, and its
+        # counters (w + 2)(h + 2) >= A + 4 sqrt(A) + 4 exceed the budget
+        A = W * H / (64 // (2 if pol else 1))
+        budget = tile_px or 40_860
+        assert A + 4 * np.sqrt(A) + 4 > budget
         return
     cc, rc = p["colcut"], p["rowcut"]
     assert cc[0] == 0 and cc[-1] == W and all(a < b for a, b in zip(cc, cc[1:]))
@@ -62,7 +66,9 @@ def test_tile_plan_invariants(W, H, foe, pol, tile_px):
         if float(v).is_integer() and 0 < v < n:
             assert int(v) in cuts
     widths, heights = np.diff(cc), np.diff(rc)
-    assert p["max_tile_px"] == int(widths.max() * heights.max()) <= p["tile_budget_px"]
+    assert p["max_tile_px"] == int(widths.max() * heights.max())
+    # the counters of the largest tile, its one-cell border included, fit the budget
+    assert int((widths.max() + 2) * (heights.max() + 2)) <= p["tile_budget_px"]
     if tile_px:
         assert p["tile_budget_px"] <= tile_px
     assert p["segments"] == p["ntx"] * p["nty"] * (2 if pol else 1) <= 64
