@@ -235,6 +235,37 @@ def main():
     host_ws = B * reps / (time.perf_counter() - a0)
     assert [(r.j_star, r.K) for r in rh] == [(r.j_star, r.K) for r in last]
 
+    # the asynchronous plan, captured once into a graph and replayed: no host
+    # synchronisation inside the search.  Steps: the default 256, and the
+    # multiple of four that this batch needs (a caller who knows its workload)
+    gstream = torch.cuda.Stream()
+    gctx = ecmd.Context(0, stream=gstream.cuda_stream)
+    need = int(max(r.steps for r in last)) + 1
+    plan_ws = {}
+    for label, msteps in (("plan_graph_256_steps", 0), (f"plan_graph_{-(-need // 4) * 4}_steps", need)):
+        plan = gctx.batch_plan(sensor, s.d_lo, s.d_hi, s.eps, max_windows=B, max_events=int(off[-1]),
+                               max_steps=msteps, **kw)
+        obuf = plan.result_buffer(B)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(gstream):
+            plan.launch(dx, dy, dt, doff, dtau, obuf)  # eager, outside the graph
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=gstream):
+            plan.launch(dx, dy, dt, doff, dtau, obuf)
+        graph.replay()
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        plan_ws[label] = round(B * reps / (time.perf_counter() - a0), 2)
+        rpl = plan.results(obuf, B)
+        assert [(r.status, r.j_star, r.K) for r in rpl] == [(0, r.j_star, r.K) for r in last]
+        del graph
+        plan.close()
+    gctx.close()
+
     # plain: one window per call, no batching
     P = min(args.plain_windows, B)
     plain_t = []
@@ -306,6 +337,7 @@ def main():
             "batched_learned": round(learned_ws, 2) if learned_ws else None,
             "batched_from_host_buffers": round(host_ws, 2),
             "plain_one_window_per_call": round(P / sum(plain_t), 2) if plain_t else None,
+            **plan_ws,
         },
         "search": {
             "nodes_expanded_mean": float(np.mean([r.nodes_expanded for r in last])),
