@@ -166,7 +166,8 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
  * per window and step (0 = 64).  tile_px: most LDS counters per image
  * tile, (w + 2)(h + 2) for a w x h tile with its one-pixel border (0 = what
  * the LDS holds; smaller values split the FOE quadrants further, trading
- * guest copies for occupancy).  graph: replay the step
+ * guest copies for occupancy).  tile_px and eval_threads both 0: the
+ * default rule of ecmd_plan picks both.  graph: replay the step
  * loop as a captured hipGraph (0 = plain launches).  group: hypotheses of
  * one window and tile evaluated per work item (0 = chosen from the batch
  * size: 1 while there are fewer than ~48 items per CU, else 2). */
@@ -175,6 +176,7 @@ typedef struct {
     int32_t tile_px;
     int32_t graph;
     int32_t group;
+    int32_t eval_threads;  /* threads per evaluation workgroup: 256, 512, 1024 (0 = 1024) */
 } ecmd_tuning;
 
 int ecmd_ctx_set_tuning(ecmd_ctx *ctx, const ecmd_tuning *tuning);
@@ -185,8 +187,12 @@ int ecmd_ctx_get_tuning(const ecmd_ctx *ctx, ecmd_tuning *out);
  * the image tiling the evaluation kernel uses — cuts at the FOE lines when
  * the FOE is an integer point strictly inside the sensor (the warp of
  * eq. (12) never moves an event across them), bands split evenly until each
- * tile's counters fit the LDS.  lds_bytes = LDS per workgroup (0 = 160 KiB,
- * gfx950); tile_px caps the tile size as ecmd_tuning.tile_px does;
+ * tile's counters fit the budget.  lds_bytes = LDS per CU (0 = 160 KiB,
+ * gfx950); tile_px caps the counters per tile as ecmd_tuning.tile_px does
+ * (0: the default rule, which takes the first of: tiles whose counters let
+ * three 512-thread workgroups share a CU, then two — each only when it
+ * cuts the image into at most 24 tiles — then one 1024-thread workgroup
+ * with the whole LDS);
  * polarity != 0 plans the two images of the polarity-aware contrast. */
 typedef struct {
     int32_t L;
@@ -196,6 +202,7 @@ typedef struct {
     int32_t tile_budget_px;  /* the limit the plan met on (w + 2)(h + 2) of the largest tile */
     int32_t colcut[65];      /* column band edges, ntx + 1 used */
     int32_t rowcut[65];      /* row band edges, nty + 1 used */
+    int32_t eval_threads;    /* threads per evaluation workgroup */
 } ecmd_plan_info;
 
 int ecmd_plan(const ecmd_sensor *sensor, const ecmd_search *search, int32_t polarity,

@@ -83,6 +83,7 @@ struct ecmd_ctx {
     int num_cu = 0;
     size_t max_lds = 0;
     size_t eval_lds = 0;   // LDS bytes of the last evaluation set-up (0 = none yet)
+    int eval_nt = 0;       // threads per evaluation workgroup of that set-up
     int eval_nb = 0;       // evaluation workgroups for that size
     // staging of host inputs
     DevBuf sx, sy, st, soff, stau, sseed, spol;
@@ -384,18 +385,52 @@ static int tile_budget_for(size_t max_lds) {
 
 static int tile_budget(ecmd_ctx* c) { return tile_budget_for(c->max_lds); }
 
+// Image tiling and evaluation workgroup size.  Explicit tuning wins
+// (tile_px caps the counters per tile, eval_threads sets the workgroup;
+// 0 = the whole LDS, 1024).  Otherwise the first of: tiles small enough for
+// three 512-thread workgroups per CU, for two, then one 1024-thread
+// workgroup on the whole LDS, where the smaller tilings may cut the image
+// into at most kMaxSmallTiles tiles.  Measured: several smaller workgroups
+// per CU hide latency that one 16-wave workgroup cannot (32 windows of
+// 346x260 in 8 tiles: 321 us per evaluation launch against 363 us in 4;
+// 64 windows of 640x480 in 24 tiles: 2.33 ms against 2.68 ms in 8), but a
+// guest copy walks its whole path in every tile it is copied to, so many
+// cuts cost more than they save (256 windows of 1280x720, D up to 2: 2.22 s
+// of evaluation in 48 tiles against 1.92 s in 24 with 1024 threads).
+constexpr int kMaxSmallTiles = 24;
+
+static bool choose_tiling(size_t max_lds, const ecmd_tuning& tu, int W, int H, float cx, float cy, int npol,
+                          Geometry& g, int& nt, int& budget) {
+    const int full = tile_budget_for(max_lds);
+    if (tu.tile_px > 0 || tu.eval_threads > 0) {
+        budget = tu.tile_px > 0 ? std::min(tu.tile_px, full) : full;
+        nt = tu.eval_threads > 0 ? tu.eval_threads : 1024;
+        return plan_geometry(W, H, cx, cy, budget, npol, g);
+    }
+    const int divs[] = {3, 2}, nts[] = {512, 512};
+    for (int k = 0; k < 2; ++k) {
+        budget = tile_budget_for(max_lds / divs[k]);
+        nt = nts[k];
+        if (plan_geometry(W, H, cx, cy, budget, npol, g) && g.nsp <= kMaxSmallTiles) return true;
+    }
+    budget = full;
+    nt = 1024;
+    return plan_geometry(W, H, cx, cy, budget, npol, g);
+}
+
 // Persistent workgroup count of the evaluation kernel for `lds` bytes of
 // LDS: as many as fit at once, at most 4 per CU.  The kernel's dynamic LDS
 // limit is raised to the device maximum once per context, so that every
 // context's launches fit whatever another context set.
-static hipError_t eval_setup(ecmd_ctx* c, size_t lds, int* nb) {
-    if (c->eval_lds != lds) {
+static hipError_t eval_setup(ecmd_ctx* c, size_t lds, int nt, int* nb) {
+    if (c->eval_lds != lds || c->eval_nt != nt) {
         hipError_t e = eval_set_lds(c->max_lds);
         if (e != hipSuccess) return e;
         int per_cu = 0;
-        if (eval_occupancy(&per_cu, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+        if (eval_occupancy(&per_cu, lds, nt) != hipSuccess || per_cu < 1) per_cu = 1;
         c->eval_lds = lds;
-        c->eval_nb = c->num_cu * std::min(per_cu, 4);
+        c->eval_nt = nt;
+        c->eval_nb = c->num_cu * std::min(per_cu, 8);
     }
     *nb = c->eval_nb;
     return hipSuccess;
@@ -420,8 +455,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     const int npol = in.pol ? 2 : 1;
     const long long M = (long long)W * H * npol;  // cells of the event image(s): the key is M*S - N^2
     Geometry g;
-    const int budget = c->tune.tile_px > 0 ? std::min(c->tune.tile_px, tile_budget(c)) : tile_budget(c);
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, npol, g))
+    int nt = 0, budget = 0;
+    if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
     Timers tm(c);
     int nblk = 0;
@@ -465,14 +500,14 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
                           T, c->seg_off.as<long long>(), InitCheck{nullptr, nullptr, 0}));
     const size_t lds = eval_lds_bytes(g.ring_px);
     int nb = 0;
-    HIPCHK(c, eval_setup(c, lds, &nb));
+    HIPCHK(c, eval_setup(c, lds, nt, &nb));
     int* h_active = (int*)c->pinned.p;
     int active = B;
     auto step_pair = [&](bool timed) -> hipError_t {
         // two steps: parity 0 then 1, so the queue pair is back in place
         for (int parity = 0; parity < 2; ++parity) {
             if (timed) tm.begin();
-            hipError_t e = launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+            hipError_t e = launch_eval(c->stream, g, nb, nt, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
                                        c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(),
                                        c->items.as<Item>(), qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd],
                                        c->part.as<Part>(), sp.HS, nullptr);
@@ -659,6 +694,7 @@ struct ecmd_batch_plan {
     int nblk_max = 0;  // prep workgroups of the largest launch
     int qcap = 0;
     size_t lds = 0;
+    int nt = 0;        // threads per evaluation workgroup
     int nb = 0;
     DevBuf wp, blk, cnt, seg_off, seg_own, cursor, ev, werr, wstat, state, front, sel, hyps, act, items, queues, part,
         n_active;
@@ -758,10 +794,12 @@ int ecmd_plan(const ecmd_sensor* sensor, const ecmd_search* search, int32_t pola
     const int L = grid_depth(search->d_lo, search->d_hi, search->eps);
     if (L < 1) return ECMD_EINVAL;
     const int npol = polarity ? 2 : 1;
-    const int budget0 = tile_budget_for(lds_bytes ? (size_t)lds_bytes : (size_t)160 * 1024);
-    const int budget = tile_px > 0 ? std::min(tile_px, budget0) : budget0;
+    ecmd_tuning tu{};
+    tu.tile_px = tile_px;
     Geometry g;
-    if (!plan_geometry(sensor->width, sensor->height, sensor->foe_x, sensor->foe_y, budget, npol, g))
+    int nt = 0, budget = 0;
+    if (!choose_tiling(lds_bytes ? (size_t)lds_bytes : (size_t)160 * 1024, tu, sensor->width, sensor->height,
+                       sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
         return ECMD_EINVAL;
     memset(out, 0, sizeof *out);
     out->L = L;
@@ -770,6 +808,7 @@ int ecmd_plan(const ecmd_sensor* sensor, const ecmd_search* search, int32_t pola
     out->nty = g.nty;
     out->max_tile_px = g.max_tile_px;
     out->tile_budget_px = budget;
+    out->eval_threads = nt;
     for (int i = 0; i <= g.ntx; ++i) out->colcut[i] = g.colcut[i];
     for (int i = 0; i <= g.nty; ++i) out->rowcut[i] = g.rowcut[i];
     return ECMD_OK;
@@ -827,6 +866,8 @@ int ecmd_ctx_set_tuning(ecmd_ctx* c, const ecmd_tuning* t) {
     if (!c || !t) return ECMD_EINVAL;
     if (t->frontier_batch < 0 || t->frontier_batch > 1024 || t->tile_px < 0 || t->group < 0 || t->group > 64)
         return fail(c, ECMD_EINVAL, "tuning out of range");
+    if (t->eval_threads != 0 && t->eval_threads != 256 && t->eval_threads != 512 && t->eval_threads != 1024)
+        return fail(c, ECMD_EINVAL, "eval_threads must be 0, 256, 512 or 1024");
     c->tune = *t;
     return ECMD_OK;
 }
@@ -849,38 +890,61 @@ int ecmd_autotune(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, const 
     c->profiling = false;
     std::vector<ecmd_result> out(B);
     const int full = tile_budget(c);
-    const int Fs[] = {16, 32, 64, 128, 256};
-    const int tiles[] = {full, full / 2, full / 4};
     double best_ms = 1e300;
     ecmd_tuning bt = saved;
-    for (int ti = 0; ti < 3; ++ti) {
-        if (ti > 0 && (long long)sensor->width * sensor->height <= tiles[ti]) break;  // one tile already
-        for (int F : Fs) {
-            for (int gv = 0; gv < 4; ++gv) {
-                const int groups[] = {0, 1, 4, 0};
-                c->tune.frontier_batch = F;
-                c->tune.tile_px = ti == 0 ? 0 : tiles[ti];
-                c->tune.graph = gv == 3 ? 1 : 0;
-                c->tune.group = groups[gv];
-                double ms = 1e300;
-                for (int rep = 0; rep < 3; ++rep) {
-                    auto t0 = std::chrono::steady_clock::now();
-                    int rc = batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, &s, flags, nullptr,
-                                          out.data());
-                    auto t1 = std::chrono::steady_clock::now();
-                    if (rc < 0 && rc != ECMD_EBUDGET && rc != ECMD_EFRONTIER) {
-                        c->tune = saved;
-                        c->profiling = prof;
-                        return rc;
-                    }
-                    if (rep > 0) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
-                }
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    bt = c->tune;
-                }
+    int rc_fail = ECMD_OK;
+    // best of two timed calls (after one untimed) for tuning t; keeps the best
+    auto trial = [&](const ecmd_tuning& t) {
+        if (rc_fail) return;
+        c->tune = t;
+        double ms = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            auto t0 = std::chrono::steady_clock::now();
+            int rc = batched_impl(c, sensor, x, y, t_rel, nullptr, offsets, tau, B, &s, flags, nullptr, out.data());
+            auto t1 = std::chrono::steady_clock::now();
+            if (rc < 0 && rc != ECMD_EBUDGET && rc != ECMD_EFRONTIER) {
+                rc_fail = rc;
+                return;
             }
+            if (rep > 0) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
         }
+        if (ms < best_ms) {
+            best_ms = ms;
+            bt = t;
+        }
+    };
+    // (1) tile size x workgroup size (smaller tiles let more workgroups share
+    // a CU), (2) frontier batch, (3) hypotheses per item and graph replay
+    ecmd_tuning t0{};
+    t0.frontier_batch = kDefaultF;
+    trial(t0);  // the default tiling rule
+    const int cands[][2] = {{full, 1024}, {full / 2, 1024}, {full / 2, 512}, {full / 3, 512}, {full / 4, 512},
+                            {full / 4, 256}};
+    for (const auto& cd : cands) {
+        ecmd_tuning t = t0;
+        t.tile_px = cd[0];
+        t.eval_threads = cd[1];
+        Geometry g;
+        if (!plan_geometry(sensor->width, sensor->height, sensor->foe_x, sensor->foe_y, cd[0], 1, g)) continue;
+        trial(t);
+    }
+    const ecmd_tuning b1 = bt;
+    for (int F : {16, 32, 128, 256}) {
+        ecmd_tuning t = b1;
+        t.frontier_batch = F;
+        trial(t);
+    }
+    const ecmd_tuning b2 = bt;
+    for (int gv = 0; gv < 3; ++gv) {
+        ecmd_tuning t = b2;
+        if (gv < 2) t.group = gv == 0 ? 1 : 4;
+        else t.graph = 1;
+        trial(t);
+    }
+    if (rc_fail) {
+        c->tune = saved;
+        c->profiling = prof;
+        return rc_fail;
     }
     c->tune = bt;
     c->profiling = prof;
@@ -941,8 +1005,8 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     const int W = sensor->width, H = sensor->height;
     const int npol = lim->polarity ? 2 : 1;
     Geometry g;
-    const int budget = c->tune.tile_px > 0 ? std::min(c->tune.tile_px, tile_budget(c)) : tile_budget(c);
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, budget, npol, g))
+    int nt = 0, budget = 0;
+    if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
     ecmd_plan_limits L2 = *lim;
     if (L2.max_steps == 0) L2.max_steps = 256;
@@ -1002,7 +1066,8 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     get(p->part, sizeof(Part) * (size_t)Bm * sp.HS * T);
     get(p->n_active, sizeof(int));
     p->lds = eval_lds_bytes(g.ring_px);
-    if (e == hipSuccess) e = eval_setup(c, p->lds, &p->nb);
+    p->nt = nt;
+    if (e == hipSuccess) e = eval_setup(c, p->lds, p->nt, &p->nb);
     if (e != hipSuccess) {
         plan_release(p);
         delete p;
@@ -1045,7 +1110,7 @@ int ecmd_plan_launch(ecmd_batch_plan* p, const float* x, const float* y, const f
     for (int step = 0; step < p->lim.max_steps; step += 4) {
         for (int k = 0; k < 4; ++k) {
             const int parity = k & 1;
-            HIPCHK(c, launch_eval(s, g, p->nb, p->lds, p->ev.as<float4>(), p->seg_off.as<long long>(),
+            HIPCHK(c, launch_eval(s, g, p->nb, p->nt, p->lds, p->ev.as<float4>(), p->seg_off.as<long long>(),
                                   p->seg_own.as<int>(), p->hyps.as<Hyp>(), p->act.as<int>(), p->items.as<Item>(),
                                   p->qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd], p->part.as<Part>(), sp.HS,
                                   nullptr));
@@ -1224,7 +1289,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     const int npol = pol ? 2 : 1;
     const long long M = (long long)W * H * npol;  // image cells per hypothesis
     Geometry g;
-    if (!plan_geometry(W, H, sensor->foe_x, sensor->foe_y, tile_budget(c), npol, g))
+    int nt = 0, budget = 0;
+    if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
         return fail(c, ECMD_EINVAL, "sensor needs more than %d tiles", kMaxTiles / npol);
     const int T = g.T;
     Inputs in;
@@ -1283,9 +1349,9 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     }
     const size_t lds = eval_lds_bytes(g.ring_px);
     int nb = 0;
-    HIPCHK(c, eval_setup(c, lds, &nb));
+    HIPCHK(c, eval_setup(c, lds, nt, &nb));
     Queue* q = c->queues.as<Queue>();
-    HIPCHK(c, launch_eval(c->stream, g, nb, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
+    HIPCHK(c, launch_eval(c->stream, g, nb, nt, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
                           c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(),
                           (int)items.size(), &q[0], &q[kXcd], c->part.as<Part>(), m, dimg));
     std::vector<Part> parts(items.size());

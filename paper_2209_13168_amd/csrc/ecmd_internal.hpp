@@ -25,7 +25,7 @@ namespace ecmd {
 typedef __int128 i128;
 
 constexpr int kMaxTiles = 64;    // tiles per sensor
-constexpr int kEvalThreads = 1024;  // threads of an evaluation workgroup
+constexpr int kEvalThreads = 1024;  // threads of the largest evaluation workgroup
 constexpr int kFrontThreads = 256;  // threads of a frontier workgroup
 
 enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2 };
@@ -157,8 +157,8 @@ hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, cons
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active);
-// q, q_reset: kXcd queues each
-hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes,
+// q, q_reset: kXcd queues each; nt: threads per workgroup (256, 512 or 1024)
+hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes,
                        const float4* ev, const long long* seg_off, const int* seg_own,
                        const Hyp* hyps, const int* act, const Item* items, int qcap, Queue* q, Queue* q_reset,
                        Part* part, int HS, unsigned* img_out);
@@ -173,7 +173,7 @@ hipError_t eval_set_lds(size_t bytes);
 // LDS bytes of the evaluation kernel for tiles of up to ring_px counters
 // (a tile of w x h pixels has (w + 2)(h + 2), its one-cell border included).
 size_t eval_lds_bytes(int ring_px);
-hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes);
+hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes, int nt);
 // Events with t in [t0, t1], compacted in order, t_rel = float(t - t0);
 // their polarities too when p is not NULL.
 hipError_t launch_select(hipStream_t s, const float* x, const float* y, const double* t, const signed char* p,

@@ -415,7 +415,8 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
 }
 
 // LDS layout of k_eval: [tile with its border: (tw + 2)(th + 2) counters]
-// (region rounded up to 16 bytes)[reduction scratch][work item].
+// (region rounded up to 16 bytes)[reduction scratch][work item, queue sizes].  The
+// reduction scratch is sized for the largest workgroup (1024 threads).
 constexpr int kEvalWaves = kEvalThreads / 64;
 
 // Counter words of the LDS tile region for tiles of up to ring_px counters
@@ -423,31 +424,35 @@ constexpr int kEvalWaves = kEvalThreads / 64;
 // 16-byte stores.
 __host__ __device__ __forceinline__ int eval_counter_words(int ring_px) { return (ring_px + 3) & ~3; }
 
-size_t eval_lds_bytes(int ring_px) { return (size_t)eval_counter_words(ring_px) * 4 + 3 * kEvalWaves * 8 + 16; }
+size_t eval_lds_bytes(int ring_px) {
+    return (size_t)eval_counter_words(ring_px) * 4 + 3 * kEvalWaves * 8 + 4 * (1 + kXcd);
+}
 
 // Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
 // items from the queue until it is empty.  For each item it clears its LDS
 // tile, bins the tile's events (point: one increment per event, interval:
 // one per pixel of the walk) with atomics that return the previous count,
 // so the sum of squares is sum(2*old + 1) with no pass over the tile.
-__global__ __launch_bounds__(kEvalThreads) void k_eval(
+template <int NT>
+__global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
     const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const int* __restrict__ act,
     const Item* __restrict__ items, int qcap, Queue* __restrict__ q, Queue* __restrict__ q_reset,
     Part* __restrict__ part, int HS, unsigned* __restrict__ img_out) {
+    constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned smem[];
     const int tid = threadIdx.x;
     unsigned* const tile = smem;
     unsigned long long* const s_red =
         reinterpret_cast<unsigned long long*>(smem + eval_counter_words(g.ring_px));
-    int* const s_item = reinterpret_cast<int*>(s_red + 3 * kEvalWaves);
+    int* const s_item = reinterpret_cast<int*>(s_red + 3 * NW);
     if (blockIdx.x == 0 && tid < kXcd && q_reset) {
         q_reset[tid].n_items = 0;
         q_reset[tid].next = 0;
     }
     const int home = blockIdx.x % kXcd;
     int qi = 0;  // queues tried so far, starting at this XCD's own (thread 0 only)
-    int qn[kXcd];  // queue sizes, read once (thread 0 only)
+    int* const qn = s_item + 1;  // queue sizes, read once (thread 0 only; in LDS, not registers)
     if (tid == 0)
         for (int r = 0; r < kXcd; ++r) qn[r] = q[(home + r) % kXcd].n_items;
     for (;;) {
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         {  // clear the counters, 16 bytes per store
             uint4* const t4 = reinterpret_cast<uint4*>(tile);
             const int n4 = (ncnt + 3) >> 2;
-            for (int i = tid; i < n4; i += kEvalThreads) t4[i] = make_uint4(0u, 0u, 0u, 0u);
+            for (int i = tid; i < n4; i += NT) t4[i] = make_uint4(0u, 0u, 0u, 0u);
         }
         __syncthreads();
 
@@ -510,13 +515,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const char* __restrict__ sev = reinterpret_cast<const char*>(ev + beg);
         const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
         const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
-        visits = (unsigned)tid < nseg ? (nseg - 1u - (unsigned)tid) / kEvalThreads + 1u : 0u;
+        visits = (unsigned)tid < nseg ? (nseg - 1u - (unsigned)tid) / NT + 1u : 0u;
         if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
             // flight, loads first, then U increments without branches.
             const float r = hp.ra;
             constexpr int U = 4;
-            constexpr unsigned S = kEvalThreads;
+            constexpr unsigned S = NT;
             unsigned i = tid;
             for (; i + (U - 1) * S < nseg; i += U * S) {
                 float4 e[U];
@@ -560,13 +565,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
             if (i < nseg) {
                 float4 e0 = at(i), e1;
                 for (;;) {
-                    e1 = at(i + kEvalThreads);  // may read past the segment: the store is padded
+                    e1 = at(i + NT);  // may read past the segment: the store is padded
                     one(e0, i);
-                    i += kEvalThreads;
+                    i += NT;
                     if (i >= nseg) break;
-                    e0 = at(i + kEvalThreads);
+                    e0 = at(i + NT);
                     one(e1, i);
-                    i += kEvalThreads;
+                    i += NT;
                     if (i >= nseg) break;
                 }
             }
@@ -580,7 +585,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         // may wrap; the workgroup's totals are exact).
         __syncthreads();
         unsigned long long hits = visits;
-        for (int k = tid; k < nring; k += kEvalThreads) {
+        for (int k = tid; k < nring; k += NT) {
             int idx;
             if (k < R.rw) idx = k;                                      // top row
             else if (k < 2 * R.rw) idx = (th + 1) * R.rw + (k - R.rw);  // bottom row
@@ -597,16 +602,16 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         const int wave = tid >> 6, lane = tid & 63;
         if (lane == 63) {
             s_red[wave] = sq;
-            s_red[kEvalWaves + wave] = hits;
-            s_red[2 * kEvalWaves + wave] = nlow;
+            s_red[NW + wave] = hits;
+            s_red[2 * NW + wave] = nlow;
         }
         __syncthreads();
         if (tid == 0) {
             unsigned long long a = 0, b = 0, c = 0;
-            for (int k = 0; k < kEvalWaves; ++k) {
+            for (int k = 0; k < NW; ++k) {
                 a += s_red[k];
-                b += s_red[kEvalWaves + k];
-                c += s_red[2 * kEvalWaves + k];
+                b += s_red[NW + k];
+                c += s_red[2 * NW + k];
             }
             Part pt;
             pt.S = a;
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
         if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
             const long long M = (long long)g.W * g.H;
             unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
-            for (int k = tid; k < tw * th; k += kEvalThreads) {
+            for (int k = tid; k < tw * th; k += NT) {
                 const int lx = k % tw, ly = k / tw;
                 im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
             }
@@ -628,20 +633,44 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval(
     }
 }
 
-hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_eval, kEvalThreads, lds_bytes);
+// The evaluation kernel for nt threads per workgroup (256, 512 or 1024).
+static const void* eval_kernel(int nt) {
+    switch (nt) {
+        case 256: return (const void*)k_eval<256>;
+        case 512: return (const void*)k_eval<512>;
+        default: return (const void*)k_eval<1024>;
+    }
+}
+
+hipError_t eval_occupancy(int* blocks_per_cu, size_t lds_bytes, int nt) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, eval_kernel(nt), nt, lds_bytes);
 }
 
 hipError_t eval_set_lds(size_t bytes) {
-    return hipFuncSetAttribute((const void*)k_eval, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    for (int nt : {256, 512, 1024}) {
+        hipError_t e = hipFuncSetAttribute(eval_kernel(nt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, size_t lds_bytes, const float4* ev,
+hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes, const float4* ev,
                        const long long* seg_off, const int* seg_own, const Hyp* hyps, const int* act,
                        const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part, int HS,
                        unsigned* img_out) {
-    k_eval<<<nblocks, kEvalThreads, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
-                                                   part, HS, img_out);
+    switch (nt) {
+        case 256:
+            k_eval<256><<<nblocks, 256, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
+                                                        part, HS, img_out);
+            break;
+        case 512:
+            k_eval<512><<<nblocks, 512, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
+                                                        part, HS, img_out);
+            break;
+        default:
+            k_eval<1024><<<nblocks, 1024, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q,
+                                                          q_reset, part, HS, img_out);
+    }
     return hipGetLastError();
 }
 

@@ -62,7 +62,7 @@ class ResultS(C.Structure):
 class PlanInfo(C.Structure):
     _fields_ = [("L", C.c_int32), ("segments", C.c_int32), ("ntx", C.c_int32), ("nty", C.c_int32),
                 ("max_tile_px", C.c_int32), ("tile_budget_px", C.c_int32), ("colcut", C.c_int32 * 65),
-                ("rowcut", C.c_int32 * 65)]
+                ("rowcut", C.c_int32 * 65), ("eval_threads", C.c_int32)]
 
 
 class PlanLimitsS(C.Structure):
@@ -72,7 +72,7 @@ class PlanLimitsS(C.Structure):
 
 class TuningS(C.Structure):
     _fields_ = [("frontier_batch", C.c_int32), ("tile_px", C.c_int32), ("graph", C.c_int32),
-                ("group", C.c_int32)]
+                ("group", C.c_int32), ("eval_threads", C.c_int32)]
 
 
 class ProfileS(C.Structure):
@@ -232,7 +232,7 @@ def plan(sensor: Sensor, d_lo: float, d_hi: float, eps: float, polarity: bool = 
         raise EcmdError(rc, "invalid plan arguments")
     return {"L": out.L, "segments": out.segments, "ntx": out.ntx, "nty": out.nty, "max_tile_px": out.max_tile_px,
             "tile_budget_px": out.tile_budget_px, "colcut": list(out.colcut[:out.ntx + 1]),
-            "rowcut": list(out.rowcut[:out.nty + 1])}
+            "rowcut": list(out.rowcut[:out.nty + 1]), "eval_threads": out.eval_threads}
 
 
 def grid_point(d_lo: float, d_hi: float, L: int, j: int) -> float:
@@ -284,14 +284,16 @@ class Context:
     def last_error(self) -> str:
         return lib().ecmd_last_error(self.h).decode()
 
-    def set_tuning(self, frontier_batch: int = 0, tile_px: int = 0, graph: bool = False, group: int = 0):
-        t = TuningS(int(frontier_batch), int(tile_px), 1 if graph else 0, int(group))
+    def set_tuning(self, frontier_batch: int = 0, tile_px: int = 0, graph: bool = False, group: int = 0,
+                   eval_threads: int = 0):
+        t = TuningS(int(frontier_batch), int(tile_px), 1 if graph else 0, int(group), int(eval_threads))
         self._check(lib().ecmd_ctx_set_tuning(self.h, C.byref(t)))
 
     def tuning(self) -> dict:
         t = TuningS()
         self._check(lib().ecmd_ctx_get_tuning(self.h, C.byref(t)))
-        return {"frontier_batch": t.frontier_batch, "tile_px": t.tile_px, "graph": bool(t.graph), "group": t.group}
+        return {"frontier_batch": t.frontier_batch, "tile_px": t.tile_px, "graph": bool(t.graph), "group": t.group,
+                "eval_threads": t.eval_threads}
 
     def autotune(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float, eps: float,
                  cache: Optional[str] = None) -> dict:
@@ -309,7 +311,8 @@ class Context:
             with open(cache) as f:
                 known = json.load(f)
             if key in known:
-                self.set_tuning(**{k: known[key][k] for k in ("frontier_batch", "tile_px", "graph", "group")})
+                self.set_tuning(**{k: known[key].get(k, 0)
+                                   for k in ("frontier_batch", "tile_px", "graph", "group", "eval_threads")})
                 return dict(known[key], cached=True)
         a = _Args()
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
@@ -320,7 +323,7 @@ class Context:
         self._check(lib().ecmd_autotune(self.h, C.byref(sensor), px, py, pt, po, ptau, B, C.byref(sp), a.flags,
                                         C.byref(best), C.byref(ms)))
         out = {"frontier_batch": best.frontier_batch, "tile_px": best.tile_px, "graph": bool(best.graph),
-               "group": best.group, "ms": ms.value}
+               "group": best.group, "eval_threads": best.eval_threads, "ms": ms.value}
         if cache:
             known = {}
             if os.path.exists(cache):

@@ -310,5 +310,5 @@ def test_host_plan_matches_the_device_search(ctx):
     x, y, t, off, tau = pack_batch([w])
     r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)[0]
     p = ecmd.plan(_sensor(s), s.d_lo, s.d_hi, s.eps)
-    assert r.L == p["L"] and p["segments"] == 4
+    assert r.L == p["L"] and (p["segments"], p["eval_threads"]) == (8, 512)
     assert r.d_hat == np.float32(ecmd.grid_point(s.d_lo, s.d_hi, p["L"], r.j_star))

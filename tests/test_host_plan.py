@@ -75,14 +75,19 @@ def test_tile_plan_invariants(W, H, foe, pol, tile_px):
 
 
 def test_tile_counts_of_the_synthetic_sensors():
-    """Default budget (160 KiB of LDS): quadrants of the 346x260 sensor, 8 tiles
-    for 640x480, 24 for 1280x720 — and twice the segments with polarity."""
-    want = {(128, 128): 4, (346, 260): 4, (640, 480): 8, (1280, 720): 24}
+    """Default rule (160 KiB of LDS): tiles for three 512-thread workgroups per
+    CU when that needs at most 24 tiles (quadrants halved on 346x260, 6 tiles
+    per quadrant on 640x480), else for two, else the whole LDS for one
+    1024-thread workgroup (1280x720: 24 tiles)."""
+    want = {(128, 128): (4, 512), (346, 260): (8, 512), (640, 480): (24, 512), (1280, 720): (24, 1024)}
     for W, H, foe in SENSORS[:4]:
         p = ecmd.plan(ecmd.sensor(W, H, foe), 0.0, 1.5, 1e-5)
         q = ecmd.plan(ecmd.sensor(W, H, foe), 0.0, 1.5, 1e-5, polarity=True)
-        assert p["segments"] == want[(W, H)], (W, H, p)
-        assert q["segments"] == 2 * p["segments"] and q["colcut"] == p["colcut"]
+        assert (p["segments"], p["eval_threads"]) == want[(W, H)], (W, H, p)
+        assert q["segments"] == 2 * p["segments"] and q["colcut"] == p["colcut"], (W, H, q)
+        for r in (p, q):  # the workgroups' LDS fit the CU: three of 512 threads, or one of 1024
+            k = 3 if r["eval_threads"] == 512 else 1
+            assert k * (4 * r["tile_budget_px"] + 420) <= 160 * 1024
 
 
 def test_plan_rejects_bad_arguments():
