@@ -51,15 +51,15 @@ EVENT_RECORD_BYTES = 16
 # HBM traffic of the evaluation kernel per launch, from two rocprofv3 --pmc
 # passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the
 # dispatches) of `bench.py --steps 2 --warmup 1 --plain-windows 0
-# --no-cpu-baseline` on the default workload, each scaled by bytes/KiB that
+# --no-cpu-baseline --no-plan` on the default workload, each scaled by bytes/KiB that
 # the same counter reads for a plain copy of 1 GiB (`bench.py
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "f61147a9f175e2492c6d5eb9da83dc9a1ea144f6491cb96155358330ef86a2db",
+    "sources_sha256": "3d7a8f810391c1493434de5518acf5dc26eb1aa0d4e0289bd5689c518342d494",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
-    "fetch_kib": 27863.8,
-    "write_kib": 457.5,
+    "fetch_kib": 31348.5,
+    "write_kib": 1009.7,
     "fetch_bytes_per_kib": 1073741824 / 524304.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
@@ -102,6 +102,9 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
                     help="trained proposal network (the step seeds the search with it when present)")
     ap.add_argument("--plain", action="store_true", help="time the search without the learned seeds")
+    ap.add_argument("--no-plan", action="store_true",
+                    help="skip the asynchronous plan legs (their finished steps launch empty kernels, which a "
+                         "kernel trace would average in)")
     ap.add_argument("--print-sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer three times (to scale HBM byte counters)")
@@ -242,7 +245,8 @@ def main():
     gctx = ecmd.Context(0, stream=gstream.cuda_stream)
     need = int(max(r.steps for r in last)) + 1
     plan_ws = {}
-    for label, msteps in (("plan_graph_256_steps", 0), (f"plan_graph_{-(-need // 4) * 4}_steps", need)):
+    legs = () if args.no_plan else (("plan_graph_256_steps", 0), (f"plan_graph_{-(-need // 4) * 4}_steps", need))
+    for label, msteps in legs:
         plan = gctx.batch_plan(sensor, s.d_lo, s.d_hi, s.eps, max_windows=B, max_events=int(off[-1]),
                                max_steps=msteps, **kw)
         obuf = plan.result_buffer(B)
