@@ -91,8 +91,12 @@ typedef struct {
  * float(d_hi * tau) < 1: the cheirality limit of eq. (11)).  gamma > 0 stops
  * Algorithm 1 once the best bound is within gamma of the incumbent in
  * contrast units.  max_nodes > 0 caps node expansions (ECMD_EBUDGET).
- * frontier_batch caps the nodes expanded together per step (0 = library
- * default); frontier_capacity caps queued nodes per window (0 = default). */
+ * frontier_batch is the expansion policy: the number of queued nodes
+ * expanded together per step, largest bound gap first (1 = best-first, one
+ * node per step as in Algorithm 1; k > 1 = the k best nodes, evaluated in
+ * one launch; 0 = the context's tuning, 64 by default); the canonical
+ * result does not depend on it.  frontier_capacity caps queued nodes per
+ * window (0 = 16384). */
 typedef struct {
     float d_lo, d_hi, eps;
     float reserved0;
@@ -414,6 +418,16 @@ void ecmd_cnn_destroy(ecmd_cnn *cnn);
 /* Copy the fp32 parameter vector (ECMD_CNN_NPARAM values, host). */
 int ecmd_cnn_get_params(ecmd_cnn *cnn, float *host_params);
 int ecmd_cnn_set_params(ecmd_cnn *cnn, const float *host_params);
+/* Checkpoint of a network: its parameters and Adam state (first and second
+ * moments, step count), so that training resumes exactly where it stopped.
+ * File layout (little-endian): the 8 bytes "ECMDCNN1", uint32 parameter
+ * count, int32 Adam step, then the parameters, the first moments and the
+ * second moments, ECMD_CNN_NPARAM fp32 values each.  ecmd_cnn_load rejects a
+ * file with another magic, count or length, or a non-finite value
+ * (ECMD_EINVAL; the network is unchanged); I/O failures are ECMD_EINVAL with
+ * the path in the message. */
+int ecmd_cnn_save(ecmd_cnn *cnn, const char *path);
+int ecmd_cnn_load(ecmd_cnn *cnn, const char *path);
 /* Forward pass on B images (bf16 bits, B*64*64): d_out[b] (fp32). */
 int ecmd_cnn_forward(ecmd_cnn *cnn, const uint16_t *imgs, int32_t B, uint32_t flags,
                      float *d_out);

@@ -1778,6 +1778,59 @@ int ecmd_cnn_set_params(ecmd_cnn* n, const float* host_params) {
     return ECMD_OK;
 }
 
+static const char kCnnMagic[8] = {'E', 'C', 'M', 'D', 'C', 'N', 'N', '1'};
+
+int ecmd_cnn_save(ecmd_cnn* n, const char* path) {
+    if (!n || !n->ctx || !path) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    c->err.clear();
+    const int np = cnn_nparam();
+    std::vector<float> buf((size_t)3 * np);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(buf.data(), n->P.p, sizeof(float) * np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(buf.data() + np, n->m.p, sizeof(float) * np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(buf.data() + 2 * np, n->v.p, sizeof(float) * np, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    FILE* f = fopen(path, "wb");
+    if (!f) return fail(c, ECMD_EINVAL, "cannot open %s for writing", path);
+    const uint32_t count = (uint32_t)np;
+    const int32_t step = n->step;
+    bool ok = fwrite(kCnnMagic, 1, 8, f) == 8 && fwrite(&count, 4, 1, f) == 1 && fwrite(&step, 4, 1, f) == 1 &&
+              fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return fail(c, ECMD_EINVAL, "writing %s failed", path);
+    return ECMD_OK;
+}
+
+int ecmd_cnn_load(ecmd_cnn* n, const char* path) {
+    if (!n || !n->ctx || !path) return ECMD_EINVAL;
+    ecmd_ctx* c = n->ctx;
+    c->err.clear();
+    const int np = cnn_nparam();
+    FILE* f = fopen(path, "rb");
+    if (!f) return fail(c, ECMD_EINVAL, "cannot open %s", path);
+    char magic[8];
+    uint32_t count = 0;
+    int32_t step = 0;
+    std::vector<float> buf((size_t)3 * np);
+    bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, kCnnMagic, 8) == 0 && fread(&count, 4, 1, f) == 1 &&
+              count == (uint32_t)np && fread(&step, 4, 1, f) == 1 && step >= 0 &&
+              fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;  // nothing after the second moments
+    fclose(f);
+    if (!ok) return fail(c, ECMD_EINVAL, "%s is not a network checkpoint of %d parameters", path, np);
+    for (size_t k = 0; k < buf.size(); ++k)
+        if (!isfinite(buf[k])) return fail(c, ECMD_EINVAL, "%s: value %zu is not finite", path, k);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(n->P.p, buf.data(), sizeof(float) * np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n->m.p, buf.data() + np, sizeof(float) * np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(n->v.p, buf.data() + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    n->step = step;
+    return ECMD_OK;
+}
+
 int ecmd_cnn_forward(ecmd_cnn* n, const uint16_t* imgs, int32_t B, uint32_t flags, float* d_out) {
     if (!n || !n->ctx || !d_out) return ECMD_EINVAL;
     ecmd_ctx* c = n->ctx;

@@ -153,6 +153,8 @@ def _load():
         "ecmd_cnn_get_params": ([vp, vp], C.c_int),
         "ecmd_cnn_set_params": ([vp, vp], C.c_int),
         "ecmd_cnn_forward": ([vp, vp, i32, u32, vp], C.c_int),
+        "ecmd_cnn_save": ([vp, C.c_char_p], C.c_int),
+        "ecmd_cnn_load": ([vp, C.c_char_p], C.c_int),
         "ecmd_cnn_grads": ([vp, vp, vp, i32, u32, vp, vp], C.c_int),
         "ecmd_cnn_train_step": ([vp, vp, vp, i32, f32, u32, vp], C.c_int),
         "ecmd_estimate_divergence_learned": ([vp, vp, C.POINTER(Sensor), vp, vp, vp, vp, vp, i32,
@@ -597,6 +599,13 @@ class Cnn:
         p = np.ascontiguousarray(p, np.float32)
         assert p.shape == (CNN_NPARAM,)
         self.ctx._check(lib().ecmd_cnn_set_params(self.h, p.ctypes.data))
+
+    def save(self, path: str):
+        """Checkpoint: parameters and Adam state (resumes training exactly)."""
+        self.ctx._check(lib().ecmd_cnn_save(self.h, os.fsencode(path)))
+
+    def load(self, path: str):
+        self.ctx._check(lib().ecmd_cnn_load(self.h, os.fsencode(path)))
 
     def forward(self, imgs):
         a = _Args()

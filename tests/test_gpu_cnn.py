@@ -70,6 +70,41 @@ def test_training_reduces_the_loss(ctx):
     net.close()
 
 
+def test_checkpoint_resumes_training_exactly(ctx, tmp_path):
+    """Parameters and Adam state saved mid-training and loaded into another
+    network continue the same trajectory bit for bit; a damaged file is
+    rejected and leaves the network as it was."""
+    from paper_2209_13168_amd import ecmd
+
+    p, x, y = _rand(9, B=8)
+    imgs = x.reshape(8, -1)
+    a = ecmd.Cnn(ctx, seed=1)
+    a.set_params(p)
+    for _ in range(3):
+        a.train_step(imgs, y, 1e-3)
+    ck = str(tmp_path / "net.ckpt")
+    a.save(ck)
+    for _ in range(2):
+        a.train_step(imgs, y, 1e-3)
+    b = ecmd.Cnn(ctx, seed=2)
+    b.load(ck)
+    for _ in range(2):
+        b.train_step(imgs, y, 1e-3)
+    assert np.array_equal(a.params().view(np.uint32), b.params().view(np.uint32))
+    raw = open(ck, "rb").read()
+    assert raw[:8] == b"ECMDCNN1" and len(raw) == 16 + 3 * 4 * ecmd.CNN_NPARAM
+    before = b.params()
+    for bad in (b"XCMDCNN1" + raw[8:], raw[:-4], raw + b"\0"):
+        open(ck, "wb").write(bad)
+        with pytest.raises(ecmd.EcmdError):
+            b.load(ck)
+    assert np.array_equal(before.view(np.uint32), b.params().view(np.uint32))
+    with pytest.raises(ecmd.EcmdError):
+        b.load(str(tmp_path / "missing.ckpt"))
+    a.close()
+    b.close()
+
+
 def test_learned_seeding_keeps_the_certified_optimum(ctx, orc):
     from paper_2209_13168_amd import ecmd
 
