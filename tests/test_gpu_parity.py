@@ -281,6 +281,39 @@ def test_graph_replay_and_tunings_match(ctx, orc):
         ctx.set_tuning(**saved)
 
 
+@pytest.mark.parametrize("tile,nt", [(0, 256), (0, 512), (0, 1024), (5000, 256), (9000, 512), (13000, 1024)])
+def test_workgroup_sizes_and_tilings_bit_exact(ctx, orc, tile, nt):
+    """Every evaluation workgroup size, on whole-LDS and on smaller tiles
+    (guest copies, bordered counters at every cut), gives the oracle's point
+    and bound values and optima."""
+    saved = ctx.tuning()
+    try:
+        ctx.set_tuning(tile_px=tile, eval_threads=nt)
+        assert ctx.tuning()["eval_threads"] == nt
+        w = config_windows("c3", [4], n_events=30_000)[0]
+        s = w.spec
+        ev = orc.Events(w.x, w.y, w.t_rel, s.tau, s.width, s.height, s.foe)
+        ds = np.array([0.0, 0.2, np.float32(s.d_true), 1.1, 1.45], np.float32)
+        S, N, _ = ctx.probe_point(_sensor(s), w.x, w.y, w.t_rel, s.tau, ds)
+        for k, d in enumerate(ds):
+            assert (int(S[k]), int(N[k])) == orc.point(ev, float(d))[:2], (k, d)
+        L = orc.depth(s.d_lo, s.d_hi, s.eps)
+        da = np.array([orc.grid_d(s.d_lo, s.d_hi, L, j) for j in (0, 1 << (L - 1), 3 << (L - 3))], np.float32)
+        db = np.array([orc.grid_d(s.d_lo, s.d_hi, L, j) for j in (1 << L, 3 << (L - 2), (3 << (L - 3)) + 7)],
+                      np.float32)
+        Sb, Nl, _ = ctx.probe_bound(_sensor(s), w.x, w.y, w.t_rel, s.tau, s.d_lo, s.d_hi, da, db)
+        for k in range(da.size):
+            assert (int(Sb[k]), int(Nl[k])) == orc.bound(ev, float(da[k]), float(db[k]))[:2], k
+        ws = config_windows("c2", range(3), n_events=8_000)
+        s2 = ws[0].spec
+        x, y, t, off, tau = pack_batch(ws)
+        got = ctx.estimate_batched(_sensor(s2), x, y, t, off, tau, s2.d_lo, s2.d_hi, 1e-4)
+        for r, wv in zip(got, ws):
+            _check_same(r, orc.bnb(orc.Events.of_window(wv), s2.d_lo, s2.d_hi, 1e-4))
+    finally:
+        ctx.set_tuning(**saved)
+
+
 def test_search_is_reproducible(ctx):
     """Node counts, steps and pixel counts are identical call after call (the
     frontier step orders everything by scans, not by atomic races)."""
