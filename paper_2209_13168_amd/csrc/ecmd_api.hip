@@ -70,7 +70,7 @@ constexpr int kChunk = 4096;          // events per prep workgroup
 constexpr int kDefaultF = 64;         // nodes expanded together
 constexpr int kDefaultCap = 16384;    // queued nodes per window
 constexpr int kMaxSteps = 1 << 20;    // hard stop of the step loop
-constexpr int kMaxRebins = 4;         // re-binnings of the events per search
+constexpr int kMaxRebins = 2;         // re-binnings of the events per search
 
 }  // namespace
 
@@ -326,7 +326,7 @@ static double key_to_double(long long hi, unsigned long long lo) {
 // device (binning ranges narrowed to the live search).  copies_out: event
 // records written, guest copies included.
 static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, float d_lo, float d_hi,
-                    int* nblk_out, bool rebin = false, long long* copies_out = nullptr) {
+                    int* nblk_out, long long* copies_out = nullptr) {
     const int T = g.T;
     std::vector<int> blk(B + 1, 0);
     for (int w = 0; w < B; ++w) {
@@ -348,7 +348,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     HIPCHK(c, c->err_flag.ensure(sizeof(int) * B));
     HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream));
     HIPCHK(c, hipMemsetAsync(c->err_flag.p, 0, sizeof(int) * B, c->stream));
-    if (!rebin) HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
+    HIPCHK(c, launch_winparam(c->stream, g, in.tau, in.off, B, d_lo, d_hi, c->wp.as<WinParam>()));
     // count + scan (scatter needs the total to size the event store)
     HIPCHK(c, launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
@@ -373,6 +373,26 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     *nblk_out = nblk;
     if (copies_out) *copies_out = total;
     return ECMD_OK;
+}
+
+// Bin the events again with the window parameters on the device (binning
+// ranges narrowed to the live search), without waiting: the windows and
+// their prep blocks are those of the last run_prep, the records cannot
+// outnumber its (a narrower range reaches a subset of the tiles), and its
+// checks of the events hold.  The scatter writes nothing if the records
+// would not fit the store; run_search checks the total afterwards.
+static hipError_t enqueue_rebin(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, int nblk) {
+    const size_t nctr = prep_counters(B, g.T);
+    hipError_t e = hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch_prep(c->stream, 0, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(), nblk,
+                    kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
+                    c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>(), -1);
+    if (e != hipSuccess) return e;
+    const long long cap = (long long)(c->ev.cap / sizeof(float4)) - kEvalThreads;
+    return launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
+                       nblk, kChunk, nullptr, c->seg_off.as<long long>(), nullptr, c->cursor.as<unsigned long long>(),
+                       c->ev.as<float4>(), nullptr, cap);
 }
 
 // Most counters (a tile's pixels and its one-cell border) that the
@@ -462,7 +482,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     int nblk = 0;
     long long copies = 0;
     tm.begin();
-    int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk, false, &copies);
+    int rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk, &copies);
     if (rc) return rc;
     tm.end(2);
     tm.cut();
@@ -501,7 +521,6 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     const size_t lds = eval_lds_bytes(g.ring_px);
     int nb = 0;
     HIPCHK(c, eval_setup(c, lds, nt, &nb));
-    int* h_active = (int*)c->pinned.p;
     int active = B;
     auto step_pair = [&](bool timed) -> hipError_t {
         // two steps: parity 0 then 1, so the queue pair is back in place
@@ -553,38 +572,66 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
             c->gkey = key;
         }
     }
-    for (int step = 0; step < kMaxSteps && active > 0; step += 4) {
+    // Blocks of four steps.  After each block the host copies the count of
+    // finished windows (and the event records) to pinned memory, but waits
+    // for block b's copy only once block b + 1 is enqueued, so the device
+    // never idles on the host; the block after the last is empty work.
+    HIPCHK(c, c->pinned.ensure(64));
+    char* const poll = (char*)c->pinned.p;  // two slots: [n_active int][pad][records int64]
+    hipEvent_t pev[2] = {pool_event(c), pool_event(c)};
+    if (!pev[0] || !pev[1]) return fail(c, ECMD_EDEVICE, "hipEventCreate failed");
+    auto enqueue_block = [&](int b) -> hipError_t {
+        hipError_t e;
         if (graph) {
-            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
-            HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+            if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return e;
+            if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return e;
         } else {
-            HIPCHK(c, step_pair(true));
-            HIPCHK(c, step_pair(true));
+            if ((e = step_pair(true)) != hipSuccess) return e;
+            if ((e = step_pair(true)) != hipSuccess) return e;
             tm.cut();
         }
-        HIPCHK(c, hipMemcpyAsync(h_active, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        active = B + *h_active;  // n_active counts finished windows down from zero
+        char* slot = poll + 16 * (b & 1);
+        if ((e = hipMemcpyAsync(slot, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+            return e;
+        if ((e = hipMemcpyAsync(slot + 8, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
+                                hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+            return e;
+        return hipEventRecord(pev[b & 1], c->stream);
+    };
+    int blocks = 0;
+    HIPCHK(c, enqueue_block(blocks++));
+    for (;;) {
         // Events copied to several tiles (guests) are binned by the whole
         // search range; once the frontier has narrowed, bin again with each
-        // window's live range (kMaxRebins times at most) to drop copies no
-        // longer needed.
-        if (active > 0 && rebins < kMaxRebins && copies > n_events + n_events / 100) {
+        // window's live range (after blocks 1 .. kMaxRebins, while the last
+        // binning known here copied more than 1% of the events) to drop
+        // copies no longer needed.
+        if (rebins < kMaxRebins && copies > n_events + n_events / 100) {
             tm.begin();
             HIPCHK(c, launch_live_range(c->stream, sp, c->state.as<WinState>(), c->front.as<Node>(),
                                         c->sel.as<Sel>(), c->wp.as<WinParam>(), B));
-            rc = run_prep(c, g, in, B, search->d_lo, search->d_hi, &nblk, true, &copies);
-            if (rc) return rc;
-            h_active = (int*)c->pinned.p;  // run_prep stages through the same buffer
+            HIPCHK(c, enqueue_rebin(c, g, in, B, nblk));
             tm.end(2);
             tm.cut();
             ++rebins;
         }
+        const bool more = blocks * 4 < kMaxSteps;
+        if (more) HIPCHK(c, enqueue_block(blocks++));
+        const int done = more ? blocks - 2 : blocks - 1;  // the block whose copy is awaited
+        HIPCHK(c, hipEventSynchronize(pev[done & 1]));
+        const char* slot = poll + 16 * (done & 1);
+        active = B + *(const int*)slot;  // n_active counts finished windows down from zero
+        copies = *(const long long*)(slot + 8);
+        if (active == 0 || !more) break;
     }
     std::vector<WinState> hs(B);
     HIPCHK(c, hipMemcpyAsync(hs.data(), c->state.p, sizeof(WinState) * B, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(poll, c->seg_off.as<long long>() + (size_t)B * T, sizeof(long long),
+                             hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     tm.collect();
+    if (*(const long long*)poll > (long long)(c->ev.cap / sizeof(float4)) - kEvalThreads)
+        return fail(c, ECMD_EDEVICE, "re-binned events exceed the event store");
     int first_status = ECMD_OK;
     for (int w = 0; w < B; ++w) {
         const WinState& s = hs[w];
