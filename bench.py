@@ -56,11 +56,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "3d7a8f810391c1493434de5518acf5dc26eb1aa0d4e0289bd5689c518342d494",
+    "sources_sha256": "20bbfd7f2f02bb14ec5700f55e66f641ecae1da78b128a78118769eb3e2b7a16",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
-    "fetch_kib": 31348.5,
-    "write_kib": 1009.7,
-    "fetch_bytes_per_kib": 1073741824 / 524304.8,
+    "fetch_kib": 26783.1,
+    "write_kib": 864.5,
+    "fetch_bytes_per_kib": 1073741824 / 524305.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
