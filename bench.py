@@ -51,7 +51,7 @@ EVENT_RECORD_BYTES = 16
 # HBM traffic of the evaluation kernel per launch, from two rocprofv3 --pmc
 # passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the
 # dispatches) of `bench.py --steps 2 --warmup 1 --plain-windows 0
-# --no-cpu-baseline --no-plan` on the default workload, each scaled by bytes/KiB that
+# --no-cpu-baseline --no-plan --no-autotune` on the default workload, each scaled by bytes/KiB that
 # the same counter reads for a plain copy of 1 GiB (`bench.py
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
@@ -102,6 +102,7 @@ def parse():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
                     help="trained proposal network (the step seeds the search with it when present)")
     ap.add_argument("--plain", action="store_true", help="time the search without the learned seeds")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuned leg")
     ap.add_argument("--no-plan", action="store_true",
                     help="skip the asynchronous plan legs (their finished steps launch empty kernels, which a "
                          "kernel trace would average in)")
@@ -226,6 +227,22 @@ def main():
         assert [(r.j_star, r.K) for r in rl] == [(r.j_star, r.K) for r in last]
         nodes_learned = float(np.mean([r.nodes_expanded for r in rl]))
 
+    # batched + learned with the launch tuning the autotuner picks for this
+    # batch (346x260 only: on the large batches one tuning pass takes minutes)
+    tuned_ws = tuned = None
+    if net is not None and not big and not args.no_autotune:
+        tuned = ctx.autotune(sensor, dx, dy, dt, doff, dtau, s.d_lo, s.d_hi, s.eps)
+        step_learned()
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        reps = max(3, args.steps // 4)
+        for _ in range(reps):
+            rt = step_learned()
+        torch.cuda.synchronize()
+        tuned_ws = B * reps / (time.perf_counter() - a0)
+        assert [(r.j_star, r.K) for r in rt] == [(r.j_star, r.K) for r in last]
+        ctx.set_tuning()  # back to the default rule for the legs below
+
     # the same batch handed over in host memory (the library stages it to
     # the device: PCIe-inclusive rate)
     ctx.estimate_batched(sensor, x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, **kw)
@@ -339,6 +356,7 @@ def main():
         "windows_per_s": {
             "batched": round(B / sec, 2),
             "batched_learned": round(learned_ws, 2) if learned_ws else None,
+            "batched_learned_autotuned": round(tuned_ws, 2) if tuned_ws else None,
             "batched_from_host_buffers": round(host_ws, 2),
             "plain_one_window_per_call": round(P / sum(plain_t), 2) if plain_t else None,
             **plan_ws,
@@ -350,6 +368,16 @@ def main():
             "point_event_evals": int(pt_ev),
             "interval_event_evals": int(bd_ev),
             "pixel_updates": int(pix),
+            "autotuned": {k: v for k, v in tuned.items() if k in ("frontier_batch", "tile_px", "graph", "group",
+                                                                   "eval_threads")} if tuned else None,
+        },
+        # per step time, and per time in the evaluation kernel (its HIP-event total over the timed steps)
+        "rates_per_s": {
+            "point_event_evals": round(pt_ev / sec, 1),
+            "interval_event_evals": round(bd_ev / sec, 1),
+            "pixel_updates": round(pix / sec, 1),
+            "event_hyp_evals_kernel_time": round(ev_hyp * args.steps / (prof["eval_ms"] / 1e3), 1)
+            if prof["eval_ms"] > 0 else None,
         },
         "roofline": roof,
     }
