@@ -45,6 +45,8 @@ OPS_INTERVAL = 16  # per event and interval: 2 endpoint warps (4 fma, 4 floor), 
 OPS_PIXEL = 12     # per upper-bound pixel increment: corner test (7 fp64), 1 step, 2 range tests, 1 index, 1 acc
 # Peak lane-operation rate: 256 CUs x 64 lanes per clock (4 SIMDs x 16) x 2.4 GHz.
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# The library's default frontier batch (nodes expanded together per window and step).
+DEFAULT_F = 96
 # Bytes of one prepared event record read by the evaluation kernel (x, y, ax, ay as fp32).
 EVENT_RECORD_BYTES = 16
 
@@ -57,7 +59,7 @@ EVENT_RECORD_BYTES = 16
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
     "sources_sha256": "20bbfd7f2f02bb14ec5700f55e66f641ecae1da78b128a78118769eb3e2b7a16",
-    "workload": {"config": "c2", "windows": 32, "frontier_batch": 64},
+    "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
     "fetch_kib": 26783.1,
     "write_kib": 864.5,
     "fetch_bytes_per_kib": 1073741824 / 524305.8,
@@ -312,7 +314,7 @@ def main():
     achieved = ops_launch / avg_launch_s if avg_launch_s > 0 else 0.0
     # each launch must read every event of every window still searching once
     alg_bytes = EVENT_RECORD_BYTES * sum(r.steps * r.n_events for r in last) * args.steps / launches
-    tkey = {"config": args.config, "windows": B, "frontier_batch": args.frontier_batch or 64}
+    tkey = {"config": args.config, "windows": B, "frontier_batch": args.frontier_batch or DEFAULT_F}
     roof = {
         "bound": "alu",
         "achieved": round(achieved / 1e9, 1),
@@ -351,7 +353,7 @@ def main():
             "windows_per_step": B,
             "events_per_window": int(n_w.mean()),
             "eps": s.eps,
-            "frontier_batch": args.frontier_batch or 64,
+            "frontier_batch": args.frontier_batch or DEFAULT_F,
         },
         "windows_per_s": {
             "batched": round(B / sec, 2),

@@ -94,7 +94,7 @@ typedef struct {
  * frontier_batch is the expansion policy: the number of queued nodes
  * expanded together per step, largest bound gap first (1 = best-first, one
  * node per step as in Algorithm 1; k > 1 = the k best nodes, evaluated in
- * one launch; 0 = the context's tuning, 64 by default); the canonical
+ * one launch; 0 = the context's tuning, 96 by default); the canonical
  * result does not depend on it.  frontier_capacity caps queued nodes per
  * window (0 = 16384). */
 typedef struct {
@@ -167,7 +167,7 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
 
 /* Launch tuning of a context, used by every search call whose
  * ecmd_search.frontier_batch is 0.  frontier_batch: nodes expanded together
- * per window and step (0 = 64).  tile_px: most LDS counters per image
+ * per window and step (0 = 96).  tile_px: most LDS counters per image
  * tile, (w + 2)(h + 2) for a w x h tile with its one-pixel border (0 = what
  * the LDS holds; smaller values split the FOE quadrants further, trading
  * guest copies for occupancy).  tile_px and eval_threads both 0: the
