@@ -58,11 +58,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "20bbfd7f2f02bb14ec5700f55e66f641ecae1da78b128a78118769eb3e2b7a16",
+    "sources_sha256": "25f6e88abba2be1ce5fef3eafb8aae42521b0d3a3a77cbb28b87d5905806b566",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 26783.1,
-    "write_kib": 864.5,
-    "fetch_bytes_per_kib": 1073741824 / 524305.8,
+    "fetch_kib": 29885.1,
+    "write_kib": 1007.8,
+    "fetch_bytes_per_kib": 1073741824 / 524306.1,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
