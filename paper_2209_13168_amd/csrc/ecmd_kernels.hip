@@ -40,6 +40,8 @@ __device__ __forceinline__ int flr_clamp(float v, int hi) {
     return cvt_flr(__builtin_amdgcn_fmed3f(v, -1.0f, (float)hi));
 }
 
+__device__ __forceinline__ unsigned umax(unsigned a, unsigned b) { return a > b ? a : b; }
+
 __device__ __forceinline__ i128 mk128(long long hi, unsigned long long lo) {
     unsigned __int128 u = ((unsigned __int128)(unsigned long long)hi << 64) | (unsigned __int128)lo;
     return (i128)u;
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(1024) void k_prep_scan(int B, int T, const int* __r
         s[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
-            long long a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            long long a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
             __syncthreads();
             s[threadIdx.x] += a;
             __syncthreads();
@@ -556,8 +558,9 @@ __global__ __launch_bounds__(NT) void k_eval(
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
                 const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
-                nlow32 += (unsigned)(i < nown) & (unsigned)(max((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
-                          (unsigned)(max((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
+                // both endpoints in the image: neither clamped to -1 (as unsigned, huge) nor to W, H
+                nlow32 += (unsigned)(i < nown) & (unsigned)(umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
+                          (unsigned)(umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
                 tile_add(org, R, kxa, kya, acc);
                 if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
             };
@@ -1389,7 +1392,7 @@ __global__ __launch_bounds__(1024) void k_select_scan(int nb, int* __restrict__ 
         s[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
-            long long a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            long long a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
             __syncthreads();
             s[threadIdx.x] += a;
             __syncthreads();
@@ -1415,7 +1418,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_write(const float* __res
     s[threadIdx.x] = keep;
     __syncthreads();
     for (int o = 1; o < kSelThreads; o <<= 1) {
-        int a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        int a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
         __syncthreads();
         s[threadIdx.x] += a;
         __syncthreads();

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(1024) void k_keep_scan(long long nb, long long* __r
         s[threadIdx.x] = v;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
-            const long long a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+            const long long a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
             __syncthreads();
             s[threadIdx.x] += a;
             __syncthreads();
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kPreThreads) void k_keep_scatter(
     s[threadIdx.x] = k;
     __syncthreads();
     for (int o = 1; o < kPreThreads; o <<= 1) {
-        const int a = threadIdx.x >= o ? s[threadIdx.x - o] : 0;
+        const int a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
         __syncthreads();
         s[threadIdx.x] += a;
         __syncthreads();
