@@ -320,9 +320,9 @@ def test_search_is_reproducible(ctx):
     ws = config_windows("c2", range(3), n_events=20_000)
     s = ws[0].spec
     x, y, t, off, tau = pack_batch(ws)
-    runs = [ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4) for _ in range(3)]
+    runs = [ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4) for _ in range(10)]
     key = lambda rs: [(r.j_star, r.K, r.nodes_expanded, r.bound_evals, r.pixel_updates, r.steps) for r in rs]
-    assert key(runs[0]) == key(runs[1]) == key(runs[2])
+    assert all(key(r) == key(runs[0]) for r in runs[1:])
 
 
 def test_measured_peaks_are_plausible(ctx):
