@@ -468,6 +468,16 @@ static int group_for(ecmd_ctx* c, int B, const Search& sp, int T) {
     return (int)std::max(1ll, std::min(2ll, work / std::max(slots, 1ll)));
 }
 
+// Group size of the search: the most hypotheses per item (group_for) and,
+// unless the tuning fixes it, the per-step rule the frontier applies: the
+// first steps of a search have few hypotheses, and groups of one then keep
+// more workgroups busy.
+static void set_groups(ecmd_ctx* c, int B, Search& sp, int T) {
+    sp.G = group_for(c, B, sp, T);
+    sp.B = B;
+    sp.gslots = c->tune.group > 0 ? 0 : std::max((long long)c->num_cu * 48, 1ll);
+}
+
 // Whole batched search on staged inputs; fills out[0..B).
 static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, int B,
                       const ecmd_search* search, int L, ecmd_result* out) {
@@ -501,7 +511,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     const int T = g.T;
-    sp.G = group_for(c, B, sp, T);
+    set_groups(c, B, sp, T);
     HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
     HIPCHK(c, c->front.ensure(sizeof(Node) * (size_t)B * sp.CAP));
     HIPCHK(c, c->sel.ensure(sizeof(Sel) * (size_t)B * sp.F));
@@ -1086,6 +1096,8 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
     sp.G = 1;
+    sp.B = 1;
+    sp.gslots = 0;
     const int Bm = L2.max_windows, T = g.T;
     p->nblk_max = (int)((L2.max_events + kChunk - 1) / kChunk) + Bm;
     p->qcap = ((Bm + kXcd - 1) / kXcd) * sp.HS * T;
@@ -1142,7 +1154,7 @@ int ecmd_plan_launch(ecmd_batch_plan* p, const float* x, const float* y, const f
     const Geometry& g = p->g;
     const int T = g.T;
     Search sp = p->sp;
-    sp.G = group_for(c, B, sp, T);
+    set_groups(c, B, sp, T);
     const long long* off = (const long long*)offsets;
     const signed char* pol = (const signed char*)polarity;
     Queue* q = p->queues.as<Queue>();

@@ -78,7 +78,9 @@ struct Search {
     int F;    // nodes expanded together per step
     int CAP;  // frontier capacity per window
     int HS;   // hypothesis slots per window (3F)
-    int G;    // hypotheses per work item
+    int G;    // hypotheses per work item (the most; see gslots)
+    int B;    // windows of the search
+    long long gslots;  // > 0: per step, G = clamp(B * hypotheses * tiles / gslots, 1, G); 0: G fixed
     long long max_nodes;
     long long gamma_key;  // stop when best K_bar - K_inc <= gamma_key (-1: gamma = 0)
     long long M;          // pixels

@@ -767,7 +767,8 @@ __device__ __forceinline__ void slot_sums(const Part* pw, int slot, int T, const
 __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
                           const Sel* sl, int n_sel, Hyp* hy, int* act, Item* items, int qcap, Queue* qf,
                           int* s_wave) {
-    const int F = sp.F, HS = sp.HS, G = sp.G;
+    const int F = sp.F, HS = sp.HS;
+    int G = sp.G;
     const int qr = w % kXcd;  // this window's queue
     Item* qitems = items + (long long)qr * qcap;
     __shared__ int s_base;
@@ -798,6 +799,10 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
         const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
         if (hp.kind != HYP_NONE) act[na + r] = h;
         na += tot;
+    }
+    if (sp.gslots > 0) {  // this step's items with one hypothesis each, all windows alike
+        const long long work = (long long)sp.B * na * nt;
+        G = (int)max(1ll, min((long long)G, work / sp.gslots));
     }
     const int ng = (na + G - 1) / G;
     if (threadIdx.x == 0) s_base = (ng * nt) ? atomicAdd(&qf[qr].n_items, ng * nt) : 0;
