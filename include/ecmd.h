@@ -173,8 +173,8 @@ int ecmd_ctx_get_profile(ecmd_ctx *ctx, ecmd_profile *out, int reset);
  * guest copies for occupancy).  tile_px and eval_threads both 0: the
  * default rule of ecmd_plan picks both.  graph: replay the step
  * loop as a captured hipGraph (0 = plain launches).  group: hypotheses of
- * one window and tile evaluated per work item (0 = chosen from the batch
- * size: 1 while there are fewer than ~48 items per CU, else 2). */
+ * one window and tile evaluated per work item (0 = chosen at every step:
+ * 1 while the step has fewer than ~48 items per CU, else 2). */
 typedef struct {
     int32_t frontier_batch;
     int32_t tile_px;
