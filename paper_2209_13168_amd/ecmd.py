@@ -110,7 +110,7 @@ class Result:
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                          "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+                          "(python paper_2209_13168_amd/build.py)")
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, u32, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_float
     sig = {
