@@ -330,7 +330,10 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 
 // Add one to every pixel of this tile that the staircase walk from pixel
 // (kx, ky) to pixel (kxb, kyb) visits (eq. (17)); the start pixel is
-// counted by the caller.  Corner decisions follow the event's ray through
+// counted by the caller.  While both coordinates still move each step takes
+// the corner test below; once one has reached its end the rest is a straight
+// run with no test (the two loops visit exactly the pixels of one loop that
+// tests every step, and skip its fp64 work on the run).  Corner decisions follow the event's ray through
 // (x, y) with direction (ax, ay), in fp64: e = |X - x||ay| - |Y - y||ax|
 // compares where the ray meets the next vertical and horizontal pixel
 // edges; within 2^-8 px of the corner both side pixels are counted.
@@ -398,22 +401,29 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
     const double aax = fabs((double)axf), aay = fabs((double)ayf);
     const double thr = (aax + aay) * 0.00390625;
     const int cx1 = sx > 0, cy1 = sy > 0;
-    do {
-        const bool dx = kx != kxb, dy = ky != kyb;
+    // both coordinates still move: which edge does the ray meet first
+    while (kx != kxb && ky != kyb) {
         const double ex = fabs((double)(kx + cx1) - x) * aay;
         const double ey = fabs((double)(ky + cy1) - y) * aax;
         const double e = ex - ey;
         const bool lo = e < -thr, hi = e > thr;
-        if (dx && dy && !lo && !hi) {  // the ray passes near the corner: both side pixels
+        if (!lo && !hi) {  // the ray passes near the corner: both side pixels
             tile_add(org, R, kx + sx, ky, acc);
             tile_add(org, R, kx, ky + sy, acc);
             acc.visits += 2;
         }
-        kx += (dx && (!dy || !hi)) ? sx : 0;
-        ky += (dy && (!dx || !lo)) ? sy : 0;
+        kx += !hi ? sx : 0;
+        ky += !lo ? sy : 0;
         tile_add(org, R, kx, ky, acc);
         acc.visits += 1;
-    } while (kx != kxb || ky != kyb);
+    }
+    // one coordinate left: a straight run
+    while (kx != kxb || ky != kyb) {
+        kx += kx != kxb ? sx : 0;
+        ky += ky != kyb ? sy : 0;
+        tile_add(org, R, kx, ky, acc);
+        acc.visits += 1;
+    }
 }
 
 // LDS layout of k_eval: [tile with its border: (tw + 2)(th + 2) counters]
@@ -814,7 +824,8 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
         it.t = tiles[ti];
         it.r0 = gi * G;
         it.cnt = min(G, na - gi * G);
-        qitems[s_base + k] = it;
+        // within a tile the groups with intervals (the longer items) first
+        qitems[s_base + ti * ng + (ng - 1 - gi)] = it;
     }
     __syncthreads();
 }

@@ -273,7 +273,7 @@ def test_graph_replay_and_tunings_match(ctx, orc):
                 for r, o in zip(got, want):
                     _check_same(r, o)
         best = ctx.autotune(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
-        assert best["frontier_batch"] in (16, 32, 64, 128, 256)
+        assert best["frontier_batch"] in (16, 32, 96, 128, 256)
         got = ctx.estimate_batched(sen, x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
         for r, o in zip(got, want):
             _check_same(r, o)
