@@ -149,9 +149,11 @@ const char *ecmd_last_error(const ecmd_ctx *ctx);
 /* Library version string. */
 const char *ecmd_version(void);
 
-/* Per-phase device timers of a context (HIP events on the context's
- * stream around every launch of the phase; off by default).  Times are
- * summed over all calls since the last reset. */
+/* Per-phase device timers of a context (off by default).  The evaluation
+ * and frontier kernels are timed by start/stop events attached to their own
+ * dispatch (kernel time only); window prep by events recorded on the
+ * context's stream around it.  Times are summed over all calls since the
+ * last reset. */
 typedef struct {
     int64_t calls;
     int64_t eval_launches;     /* hypothesis evaluation kernel (eqs. (13)-(20)) */

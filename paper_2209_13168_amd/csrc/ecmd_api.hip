@@ -150,6 +150,21 @@ struct Timers {
     }
     // other work is enqueued next: the following launch records its own start
     void cut() { last = nullptr; }
+    // A pair of events for one kernel launched with them (the dispatch takes
+    // the kernel's own start and end times; no event is recorded on the
+    // stream), or two nulls when not profiling.
+    void pair(int kind, hipEvent_t& a, hipEvent_t& b) {
+        a = b = nullptr;
+        if (!c->profiling) return;
+        a = pool_event(c);
+        b = pool_event(c);
+        if (!a || !b) {
+            a = b = nullptr;
+            return;
+        }
+        marks.push_back(Mark{a, b, kind});
+        last = nullptr;
+    }
     // after the stream has been synchronised
     void collect() {
         if (!c->profiling) return;
@@ -535,20 +550,19 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     auto step_pair = [&](bool timed) -> hipError_t {
         // two steps: parity 0 then 1, so the queue pair is back in place
         for (int parity = 0; parity < 2; ++parity) {
-            if (timed) tm.begin();
+            hipEvent_t a = nullptr, b = nullptr;
+            if (timed) tm.pair(0, a, b);
             hipError_t e = launch_eval(c->stream, g, nb, nt, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
                                        c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(),
                                        c->items.as<Item>(), qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd],
-                                       c->part.as<Part>(), sp.HS, nullptr);
+                                       c->part.as<Part>(), sp.HS, nullptr, a, b);
             if (e != hipSuccess) return e;
-            if (timed) tm.end(0);
-            if (timed) tm.begin();
+            if (timed) tm.pair(1, a, b);
             e = launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
                                 c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(), c->hyps.as<Hyp>(),
                                 c->act.as<int>(), c->part.as<Part>(), c->items.as<Item>(), qcap,
-                                &q[(1 - parity) * kXcd], c->n_active.as<int>());
+                                &q[(1 - parity) * kXcd], c->n_active.as<int>(), a, b);
             if (e != hipSuccess) return e;
-            if (timed) tm.end(1);
         }
         return hipSuccess;
     };

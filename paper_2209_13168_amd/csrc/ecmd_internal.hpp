@@ -156,14 +156,16 @@ struct InitCheck {
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off, InitCheck chk);
+// t0, t1 (nullable): events that take the kernel's own start and end times
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
-                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active);
+                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active,
+                           hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // q, q_reset: kXcd queues each; nt: threads per workgroup (256, 512 or 1024)
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes,
                        const float4* ev, const long long* seg_off, const int* seg_own,
                        const Hyp* hyps, const int* act, const Item* items, int qcap, Queue* q, Queue* q_reset,
-                       Part* part, int HS, unsigned* img_out);
+                       Part* part, int HS, unsigned* img_out, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_rates(hipStream_t s, const float* d_a, const float* d_b, int m, float tau, Hyp* hyps);
 hipError_t launch_probe_pixels(hipStream_t s, const float* x, const float* y, const float* t_rel,
                                long long n, float tau, float d, int W, int H, float cx, float cy,

@@ -4,6 +4,8 @@
 // contrast eq. (14), upper bound eqs. (15)-(20), branch and bound Alg. 1.
 // Built with -ffp-contract=off: every fp32/fp64 operation below rounds
 // exactly as written (the readings are listed in include/ecmd.h).
+#include <hip/hip_ext.h>
+
 #include "ecmd_internal.hpp"
 
 namespace ecmd {
@@ -670,19 +672,20 @@ hipError_t eval_set_lds(size_t bytes) {
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes, const float4* ev,
                        const long long* seg_off, const int* seg_own, const Hyp* hyps, const int* act,
                        const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part, int HS,
-                       unsigned* img_out) {
+                       unsigned* img_out, hipEvent_t t0, hipEvent_t t1) {
+    // the events (nullable) take the kernel's start and end times from its dispatch
     switch (nt) {
         case 256:
-            k_eval<256><<<nblocks, 256, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
-                                                        part, HS, img_out);
+            hipExtLaunchKernelGGL(k_eval<256>, dim3(nblocks), dim3(256), (uint32_t)lds_bytes, s, t0, t1, 0u, g, ev,
+                                  seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
             break;
         case 512:
-            k_eval<512><<<nblocks, 512, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset,
-                                                        part, HS, img_out);
+            hipExtLaunchKernelGGL(k_eval<512>, dim3(nblocks), dim3(512), (uint32_t)lds_bytes, s, t0, t1, 0u, g, ev,
+                                  seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
             break;
         default:
-            k_eval<1024><<<nblocks, 1024, lds_bytes, s>>>(g, ev, seg_off, seg_own, hyps, act, items, qcap, q,
-                                                          q_reset, part, HS, img_out);
+            hipExtLaunchKernelGGL(k_eval<1024>, dim3(nblocks), dim3(1024), (uint32_t)lds_bytes, s, t0, t1, 0u, g,
+                                  ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
     }
     return hipGetLastError();
 }
@@ -1179,10 +1182,11 @@ hipError_t launch_live_range(hipStream_t s, const Search& sp, const WinState* st
 
 hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
-                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active) {
+                           const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active, hipEvent_t t0,
+                           hipEvent_t t1) {
     if (B <= 0) return hipSuccess;
-    k_frontier<<<B, NTF, 0, s>>>(sp, wp, B, T, seg_off, st, front, sel, hyps, act, part, items, qcap, q_fill,
-                                n_active);
+    hipExtLaunchKernelGGL(k_frontier, dim3(B), dim3(NTF), 0u, s, t0, t1, 0u, sp, wp, B, T, seg_off, st, front, sel,
+                          hyps, act, part, items, qcap, q_fill, n_active);
     return hipGetLastError();
 }
 
