@@ -58,11 +58,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "3b8df9cce89c5c38b6440b349fab7d3ce62ae8e80826c4775e5882b95f31e649",
+    "sources_sha256": "9ceacfd706ba662d4122bdb76e6022d55c5574a76abc7610af9a6428caa4d909",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 24309.2,
-    "write_kib": 1040.3,
-    "fetch_bytes_per_kib": 1073741824 / 524305.0,
+    "fetch_kib": 24367.2,
+    "write_kib": 1040.5,
+    "fetch_bytes_per_kib": 1073741824 / 524304.6,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",

@@ -341,6 +341,8 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // edges; within 2^-8 px of the corner both side pixels are counted.
 // Each increment returns the previous count; it is added to `sumold` one
 // increment later (`pend`), so the wait for it overlaps the next step.
+// The corner test computes X - x as kx - (x - 1) or kx - x (the edge ahead
+// is kx + 1 or kx), the same fp64 value as X - x, so decisions do not change.
 // Pixels outside the tile are clamped onto its one-cell border (`Ring`),
 // whose counts are removed at the end.
 struct WalkAcc {
@@ -388,43 +390,61 @@ __device__ __forceinline__ unsigned* ring_at(unsigned* org, const Ring& R, int k
     return org + mad24(ky, R.rw, kx);
 }
 
-__device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py, WalkAcc& acc) {
-    const int cx = clampi(px, R.xlo, R.vxhi), cy = clampi(py, R.ylo, R.vyhi);
-    const unsigned old = atomicAdd(ring_at(org, R, cx, cy), 1u);
+__device__ __forceinline__ void lds_inc(unsigned* p, WalkAcc& acc) {
+    const unsigned old = atomicAdd(p, 1u);
     acc.sumold += acc.pend;
     acc.pend = old;
 }
 
+__device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py, WalkAcc& acc) {
+    const int cx = clampi(px, R.xlo, R.vxhi), cy = clampi(py, R.ylo, R.vyhi);
+    lds_inc(ring_at(org, R, cx, cy), acc);
+}
+
 __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, int ky, int kxb,
                                           int kyb, float xf, float yf, float axf, float ayf, WalkAcc& acc) {
-    const int sx = (kxb > kx) - (kxb < kx);
-    const int sy = (kyb > ky) - (kyb < ky);
-    const double x = (double)xf, y = (double)yf;
-    const double aax = fabs((double)axf), aay = fabs((double)ayf);
-    const double thr = (aax + aay) * 0.00390625;
-    const int cx1 = sx > 0, cy1 = sy > 0;
-    // both coordinates still move: which edge does the ray meet first
-    while (kx != kxb && ky != kyb) {
-        const double ex = fabs((double)(kx + cx1) - x) * aay;
-        const double ey = fabs((double)(ky + cy1) - y) * aax;
-        const double e = ex - ey;
-        const bool lo = e < -thr, hi = e > thr;
-        if (!lo && !hi) {  // the ray passes near the corner: both side pixels
-            tile_add(org, R, kx + sx, ky, acc);
-            tile_add(org, R, kx, ky + sy, acc);
-            acc.visits += 2;
-        }
-        kx += !hi ? sx : 0;
-        ky += !lo ? sy : 0;
-        tile_add(org, R, kx, ky, acc);
-        acc.visits += 1;
+    // step direction of each coordinate (not used once it is at its end)
+    const bool px = kxb > kx, py = kyb > ky;
+    const int sx = px ? 1 : -1, sy = py ? 1 : -1;
+    // increments: one per unit step of either coordinate, and one more for
+    // each corner that counts both side pixels (that step moves both
+    // coordinates and adds three)
+    acc.visits += (unsigned)(abs(kxb - kx) + abs(kyb - ky));
+    if (kx != kxb && ky != kyb) {
+        // the edges ahead are X = kx + px and Y = ky + py; with the origin
+        // moved to (x - px, y - py) (exact in fp64), X - x = kx - xo exactly
+        const double xo = (double)xf - (double)px, yo = (double)yf - (double)py;
+        const double aax = fabs((double)axf), aay = fabs((double)ayf);
+        const double thr = (aax + aay) * 0.00390625;
+        // both coordinates still move: which edge does the ray meet first
+        do {
+            const double ex = fabs((double)kx - xo) * aay;
+            const double ey = fabs((double)ky - yo) * aax;
+            const double e = ex - ey;
+            const bool lo = e < -thr, hi = e > thr;
+            if (!lo && !hi) {  // the ray passes near the corner: both side pixels
+                tile_add(org, R, kx + sx, ky, acc);
+                tile_add(org, R, kx, ky + sy, acc);
+                acc.visits += 1;
+            }
+            kx += !hi ? sx : 0;
+            ky += !lo ? sy : 0;
+            tile_add(org, R, kx, ky, acc);
+        } while (kx != kxb && ky != kyb);
     }
-    // one coordinate left: a straight run
-    while (kx != kxb || ky != kyb) {
-        kx += kx != kxb ? sx : 0;
-        ky += ky != kyb ? sy : 0;
-        tile_add(org, R, kx, ky, acc);
-        acc.visits += 1;
+    // one coordinate left: a straight run along a row or a column
+    if (kx != kxb) {
+        const int cy = clampi(ky, R.ylo, R.vyhi);
+        do {
+            kx += sx;
+            lds_inc(org + mad24(cy, R.rw, clampi(kx, R.xlo, R.vxhi)), acc);
+        } while (kx != kxb);
+    } else {
+        const int cx = clampi(kx, R.xlo, R.vxhi);
+        while (ky != kyb) {
+            ky += sy;
+            lds_inc(org + mad24(clampi(ky, R.ylo, R.vyhi), R.rw, cx), acc);
+        }
     }
 }
 
