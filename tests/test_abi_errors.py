@@ -20,6 +20,8 @@ def test_null_handles_and_outputs_are_rejected():
     assert L.ecmd_cnn_create(None, C.c_uint64(0), None) == ecmd.EINVAL
     assert L.ecmd_cnn_save(None, b"x") == ecmd.EINVAL
     assert L.ecmd_cnn_load(None, b"x") == ecmd.EINVAL
+    assert L.ecmd_ctx_set_profiling(None, 1) == ecmd.EINVAL
+    assert L.ecmd_ctx_get_profile(None, None, 0) == ecmd.EINVAL
     assert L.ecmd_last_error(None) == b"NULL context"
     # destroying nothing is a no-op
     L.ecmd_ctx_destroy(None)

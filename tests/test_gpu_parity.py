@@ -325,6 +325,40 @@ def test_search_is_reproducible(ctx):
     assert all(key(r) == key(runs[0]) for r in runs[1:])
 
 
+def test_profiling_timers(ctx):
+    """The per-phase timers (kernel times taken from each launch's own
+    dispatch): every evaluation launch pairs with a frontier launch, the
+    times are positive and fit inside the calls' wall time, a reset clears
+    them, and timing the kernels changes no result."""
+    import time
+
+    ws = config_windows("c2", range(4), n_events=20_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    key = lambda rs: [(r.j_star, r.K, r.nodes_expanded, r.bound_evals, r.pixel_updates, r.steps) for r in rs]
+    ref = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+    ctx.set_profiling(True)
+    try:
+        ctx.profile(reset=True)
+        t0 = time.perf_counter()
+        runs = [ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4) for _ in range(3)]
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        p = ctx.profile(reset=True)
+        cleared = ctx.profile()
+    finally:
+        ctx.set_profiling(False)
+    assert all(key(r) == key(ref) for r in runs)
+    assert p["calls"] == 3
+    assert p["eval_launches"] >= 3 * max(r.steps for r in ref)
+    assert p["frontier_launches"] == p["eval_launches"]
+    assert p["eval_ms"] > 0 and p["frontier_ms"] > 0 and p["prep_ms"] > 0
+    assert p["eval_ms"] + p["frontier_ms"] + p["prep_ms"] < wall_ms
+    assert cleared["calls"] == 0 and cleared["eval_launches"] == 0 and cleared["eval_ms"] == 0.0
+    # off again: nothing is accumulated
+    ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
+    assert ctx.profile()["calls"] == 0
+
+
 def test_measured_peaks_are_plausible(ctx):
     """The calibration kernels run and give rates within the chip's reach
     (returning LDS atomics under 32 banks x 2.4 GHz x 256 CUs; HBM read
