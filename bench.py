@@ -58,11 +58,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "9ceacfd706ba662d4122bdb76e6022d55c5574a76abc7610af9a6428caa4d909",
+    "sources_sha256": "a43bba3d6c8318660588bcf9662481e147ddc1465bb020df6df1aac3954ead2d",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 24367.2,
-    "write_kib": 1040.5,
-    "fetch_bytes_per_kib": 1073741824 / 524304.6,
+    "fetch_kib": 24481.1,
+    "write_kib": 1040.2,
+    "fetch_bytes_per_kib": 1073741824 / 524304.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",

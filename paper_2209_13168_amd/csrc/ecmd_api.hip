@@ -379,9 +379,9 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
         if (errf[w])
             return fail(c, ECMD_EINVAL, "window %d: an event has a non-finite coordinate or t_rel outside [0, tau]",
                         w);
-    // one stride of padding: the evaluation kernel prefetches up to
-    // kEvalThreads records past the end of a segment
-    HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)(total + kEvalThreads)));
+    // padding: the evaluation kernel prefetches up to kEvalPad records past
+    // the end of a segment
+    HIPCHK(c, c->ev.ensure(sizeof(float4) * (size_t)(total + kEvalPad)));
     HIPCHK(c, launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                           nblk, kChunk, nullptr, nullptr, nullptr, c->cursor.as<unsigned long long>(),
                           c->ev.as<float4>(), nullptr, -1));
@@ -404,7 +404,7 @@ static hipError_t enqueue_rebin(ecmd_ctx* c, const Geometry& g, const Inputs& in
                     kChunk, c->cnt_own.as<int>(), c->seg_off.as<long long>(), c->seg_own.as<int>(),
                     c->cursor.as<unsigned long long>(), nullptr, c->err_flag.as<int>(), -1);
     if (e != hipSuccess) return e;
-    const long long cap = (long long)(c->ev.cap / sizeof(float4)) - kEvalThreads;
+    const long long cap = (long long)(c->ev.cap / sizeof(float4)) - kEvalPad;
     return launch_prep(c->stream, 1, g, in.x, in.y, in.t, in.pol, in.off, c->wp.as<WinParam>(), B, c->blk.as<int>(),
                        nblk, kChunk, nullptr, c->seg_off.as<long long>(), nullptr, c->cursor.as<unsigned long long>(),
                        c->ev.as<float4>(), nullptr, cap);
@@ -654,7 +654,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     tm.collect();
-    if (*(const long long*)poll > (long long)(c->ev.cap / sizeof(float4)) - kEvalThreads)
+    if (*(const long long*)poll > (long long)(c->ev.cap / sizeof(float4)) - kEvalPad)
         return fail(c, ECMD_EDEVICE, "re-binned events exceed the event store");
     int first_status = ECMD_OK;
     for (int w = 0; w < B; ++w) {
@@ -1126,7 +1126,7 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     get(p->seg_off, sizeof(long long) * ((size_t)Bm * T + 1));
     get(p->seg_own, sizeof(int) * (size_t)Bm * T);
     get(p->cursor, sizeof(unsigned long long) * nctr);
-    get(p->ev, sizeof(float4) * (size_t)(L2.max_records + kEvalThreads));  // padded as in the synchronous call
+    get(p->ev, sizeof(float4) * (size_t)(L2.max_records + kEvalPad));  // padded as in the synchronous call
     get(p->werr, sizeof(int) * Bm);
     get(p->wstat, sizeof(int) * Bm);
     get(p->state, sizeof(WinState) * Bm);

@@ -26,6 +26,7 @@ typedef __int128 i128;
 
 constexpr int kMaxTiles = 64;    // tiles per sensor
 constexpr int kEvalThreads = 1024;  // threads of the largest evaluation workgroup
+constexpr int kEvalPad = 2 * kEvalThreads;  // records after the event store: the evaluation kernel prefetches up to two workgroup strides past a segment's end
 constexpr int kFrontThreads = 256;  // threads of a frontier workgroup
 
 enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2 };

@@ -596,16 +596,23 @@ __global__ __launch_bounds__(NT) void k_eval(
                 tile_add(org, R, kxa, kya, acc);
                 if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
             };
+            // two events in flight ahead of the one being binned (the
+            // loads may read up to two strides past the segment: the store is
+            // padded by kEvalPad records)
             unsigned i = tid;
             if (i < nseg) {
-                float4 e0 = at(i), e1;
+                float4 e0 = at(i), e1 = at(i + NT), e2;
                 for (;;) {
-                    e1 = at(i + NT);  // may read past the segment: the store is padded
+                    e2 = at(i + 2 * NT);
                     one(e0, i);
                     i += NT;
                     if (i >= nseg) break;
-                    e0 = at(i + NT);
+                    e0 = at(i + 2 * NT);
                     one(e1, i);
+                    i += NT;
+                    if (i >= nseg) break;
+                    e1 = at(i + 2 * NT);
+                    one(e2, i);
                     i += NT;
                     if (i >= nseg) break;
                 }
