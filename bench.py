@@ -58,11 +58,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "a43bba3d6c8318660588bcf9662481e147ddc1465bb020df6df1aac3954ead2d",
+    "sources_sha256": "0dd592a73c33844eb9792f224c1c4c0ec68741a4ec394fb7ec208d26512b39c4",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 24481.1,
-    "write_kib": 1040.2,
-    "fetch_bytes_per_kib": 1073741824 / 524304.8,
+    "fetch_kib": 24386.7,
+    "write_kib": 1040.1,
+    "fetch_bytes_per_kib": 1073741824 / 524305.0,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
@@ -303,7 +303,7 @@ def main():
         plain_t.append(time.perf_counter() - a)
         assert (rp.j_star, rp.K) == (last[k].j_star, last[k].K)
 
-    # measured denominators: conflict-free returning LDS atomics, HBM stream read
+    # measured denominators: conflict-free LDS atomic adds (no return), HBM stream read
     peaks = ctx.measure_peaks()
 
     # roofline of the evaluation kernel (all its launches in the timed region)
@@ -328,7 +328,7 @@ def main():
         "avg_launch_us": round(avg_launch_s * 1e6, 2),
         "launches_per_step": round(launches / args.steps, 2),
         "eval_share_of_step": round(prof["eval_ms"] / 1e3 / args.steps / sec, 3),
-        # one returning LDS atomic per event and hypothesis (walk steps add more)
+        # one LDS atomic add per event and hypothesis (walk steps add more)
         "lds_atomics_per_s_at_least": round((pt_ev + bd_ev) * args.steps / (prof["eval_ms"] / 1e3), 1)
         if prof["eval_ms"] > 0 else None,
         "lds_atomic_peak_measured": round(peaks["lds_atomics_per_s"], 1),

@@ -221,8 +221,8 @@ float ecmd_grid_point(float d_lo, float d_hi, uint32_t L, uint32_t j);
 
 /* Measured roofline denominators of this device (run on the context's
  * stream, timed with HIP events, best of three): the rate of conflict-free
- * returning LDS atomic adds (lane operations per second, the operation the
- * event-image histograms use; 2 workgroups of 1024 lanes per CU, each lane
+ * LDS atomic adds that return nothing (lane operations per second, the
+ * operation the event-image histograms use; 2 workgroups of 1024 lanes per CU, each lane
  * on its own counter) and the HBM read bandwidth of a streaming sum over
  * hbm_bytes (0 = 4 GiB, allocated for the call and freed). */
 int ecmd_measure_peaks(ecmd_ctx *ctx, int64_t hbm_bytes, double *lds_atomics_per_s,

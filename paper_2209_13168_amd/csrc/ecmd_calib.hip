@@ -1,7 +1,7 @@
 // Calibration kernels for the roofline of the evaluation kernel: the rate of
-// conflict-free returning LDS atomic adds (the operation the event-image
-// histograms use, counted per lane) and the HBM stream-read bandwidth, both
-// measured on the device the context runs on.
+// conflict-free LDS atomic adds without return (the operation the
+// event-image histograms use, counted per lane) and the HBM stream-read
+// bandwidth, both measured on the device the context runs on.
 #include "ecmd_internal.hpp"
 
 namespace ecmd {
@@ -9,20 +9,21 @@ namespace ecmd {
 constexpr int kCalThreads = 1024;
 constexpr int kCalWords = 8192;  // 32 KiB of counters per workgroup
 
-// Every lane adds 1 to its own counter word, `iters` times, and keeps the
-// returned values (so the returning form is timed); lanes of a wave hit 64
+// Every lane adds 1 to its own counter word, `iters` times, without using
+// the old value (the form the histograms use); lanes of a wave hit 64
 // consecutive words, i.e. no two lanes of an access share a bank.
 __global__ __launch_bounds__(kCalThreads) void k_lds_atomics(int iters, unsigned* __restrict__ sink) {
     __shared__ unsigned cnt[kCalWords];
     for (int i = threadIdx.x; i < kCalWords; i += kCalThreads) cnt[i] = 0u;
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned acc = 0;
     for (int k = 0; k < iters; ++k) {
         const int w = ((wave * 8 + (k & 7)) * 64 + lane) & (kCalWords - 1);
-        acc += atomicAdd(&cnt[w], 1u);
+        atomicAdd(&cnt[w], 1u);
     }
-    if (acc == 0xFFFFFFFFu) sink[blockIdx.x] = acc;  // keeps the returned values live
+    __syncthreads();
+    const unsigned v = cnt[threadIdx.x & (kCalWords - 1)];
+    if (v == 0xFFFFFFFFu) sink[blockIdx.x] = v;  // keeps the counters observable
 }
 
 // Sum of a buffer of float4, grid-stride, one partial per workgroup.

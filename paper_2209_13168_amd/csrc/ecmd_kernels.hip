@@ -339,15 +339,13 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // (x, y) with direction (ax, ay), in fp64: e = |X - x||ay| - |Y - y||ax|
 // compares where the ray meets the next vertical and horizontal pixel
 // edges; within 2^-8 px of the corner both side pixels are counted.
-// Each increment returns the previous count; it is added to `sumold` one
-// increment later (`pend`), so the wait for it overlaps the next step.
+// Increments do not return the old count, so no step waits on the LDS;
+// the item's sum of squares comes from one pass over the tile afterwards.
 // The corner test computes X - x as kx - (x - 1) or kx - x (the edge ahead
 // is kx + 1 or kx), the same fp64 value as X - x, so decisions do not change.
 // Pixels outside the tile are clamped onto its one-cell border (`Ring`),
 // whose counts are removed at the end.
 struct WalkAcc {
-    unsigned long long sumold;
-    unsigned pend;
     unsigned visits;  // walk increments (the start pixels are counted by the caller)
 };
 
@@ -390,10 +388,8 @@ __device__ __forceinline__ unsigned* ring_at(unsigned* org, const Ring& R, int k
     return org + mad24(ky, R.rw, kx);
 }
 
-__device__ __forceinline__ void lds_inc(unsigned* p, WalkAcc& acc) {
-    const unsigned old = atomicAdd(p, 1u);
-    acc.sumold += acc.pend;
-    acc.pend = old;
+__device__ __forceinline__ void lds_inc(unsigned* p, WalkAcc&) {
+    atomicAdd(p, 1u);  // the old count is not used: no wait for it
 }
 
 __device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py, WalkAcc& acc) {
@@ -465,8 +461,9 @@ size_t eval_lds_bytes(int ring_px) {
 // Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
 // items from the queue until it is empty.  For each item it clears its LDS
 // tile, bins the tile's events (point: one increment per event, interval:
-// one per pixel of the walk) with atomics that return the previous count,
-// so the sum of squares is sum(2*old + 1) with no pass over the tile.
+// one per pixel of the walk) with LDS atomic adds that return nothing, then
+// sums the squares of the tile's counters in one 16-byte-wide pass and
+// removes the border counters' share.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
@@ -542,7 +539,7 @@ __global__ __launch_bounds__(NT) void k_eval(
         }
         __syncthreads();
 
-        unsigned long long sumold = 0, nlow = 0;
+        unsigned long long nlow = 0;
         unsigned visits = 0;  // increments by this thread: one per event, plus walk steps
         // the segment's events, indexed from its start with 32-bit offsets
         // (byte offsets fit 32 bits: a segment holds fewer than 2^28 events)
@@ -568,22 +565,19 @@ __global__ __launch_bounds__(NT) void k_eval(
                     const int ky = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e[k].w, r, e[k].y), fylo, fyhi));
                     a[k] = mad24(ky, R.rw, kx);
                 }
-                unsigned old[U];
 #pragma unroll
-                for (int k = 0; k < U; ++k) old[k] = atomicAdd(org + a[k], 1u);
-#pragma unroll
-                for (int k = 0; k < U; ++k) sumold += old[k];
+                for (int k = 0; k < U; ++k) atomicAdd(org + a[k], 1u);
             }
             for (; i < nseg; i += S) {
                 const float4 e = at(i);
                 const int kx = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e.z, r, e.x), fxlo, fxhi));
                 const int ky = cvt_flr(__builtin_amdgcn_fmed3f(fmaf(e.w, r, e.y), fylo, fyhi));
-                sumold += atomicAdd(ring_at(org, R, kx, ky), 1u);
+                atomicAdd(ring_at(org, R, kx, ky), 1u);
             }
         } else {
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
-            WalkAcc acc{0ull, 0u, 0u};
+            WalkAcc acc{0u};
             unsigned nlow32 = 0;
             const auto one = [&](const float4& e, unsigned i) {
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
@@ -617,26 +611,33 @@ __global__ __launch_bounds__(NT) void k_eval(
                     if (i >= nseg) break;
                 }
             }
-            sumold = acc.sumold + acc.pend;
             visits += acc.visits;
             nlow = nlow32;
         }
-        // Remove the border counters: a counter's m increments returned 0, 1,
-        // .., m-1; then the sum of squares is sum(2*old + 1) over the in-tile
-        // increments.  Each thread takes some border counters (its own sums
-        // may wrap; the workgroup's totals are exact).
+        // Sum of squares over the whole counter region, 16 bytes per read,
+        // then the border counters' squares and counts removed.  Each thread
+        // takes some counters (its own sums may wrap; the workgroup's totals
+        // are exact).
         __syncthreads();
-        unsigned long long hits = visits;
+        unsigned long long sq = 0, hits = visits;
+        {
+            const uint4* const t4 = reinterpret_cast<const uint4*>(tile);
+            const int n4 = (ncnt + 3) >> 2;  // the clear zeroed the rounded-up region
+            for (int i = tid; i < n4; i += NT) {
+                const uint4 v = t4[i];
+                sq += (unsigned long long)v.x * v.x + (unsigned long long)v.y * v.y +
+                      (unsigned long long)v.z * v.z + (unsigned long long)v.w * v.w;
+            }
+        }
         for (int k = tid; k < nring; k += NT) {
             int idx;
             if (k < R.rw) idx = k;                                      // top row
             else if (k < 2 * R.rw) idx = (th + 1) * R.rw + (k - R.rw);  // bottom row
             else idx = (1 + ((k - 2 * R.rw) >> 1)) * R.rw + (((k - 2 * R.rw) & 1) ? R.rw - 1 : 0);
             const unsigned m = tile[idx];
-            sumold -= (unsigned long long)m * (m - 1ull) / 2ull;
+            sq -= (unsigned long long)m * m;
             hits -= m;
         }
-        unsigned long long sq = 2ull * sumold + hits;
         // block reduction of (S, hits, nlow)
         sq = wave_total(sq);
         hits = wave_total(hits);

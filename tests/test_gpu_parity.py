@@ -361,7 +361,7 @@ def test_profiling_timers(ctx):
 
 def test_measured_peaks_are_plausible(ctx):
     """The calibration kernels run and give rates within the chip's reach
-    (returning LDS atomics under 32 banks x 2.4 GHz x 256 CUs; HBM read
+    (LDS atomic adds under 64 lanes per cycle x 2.4 GHz x 256 CUs; HBM read
     under the 8 TB/s specification)."""
     p = ctx.measure_peaks(1 << 30)
     assert 1e11 < p["lds_atomics_per_s"] < 256 * 64 * 2.4e9 * 1.05
