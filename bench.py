@@ -58,9 +58,9 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "0dd592a73c33844eb9792f224c1c4c0ec68741a4ec394fb7ec208d26512b39c4",
+    "sources_sha256": "8db46e307cca69233b8996d30923f4d8e5d4867dd1ac80bd9595762c61308c8e",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 24386.7,
+    "fetch_kib": 24487.1,
     "write_kib": 1040.1,
     "fetch_bytes_per_kib": 1073741824 / 524305.0,
     "write_bytes_per_kib": 1073741824 / 1048576.0,

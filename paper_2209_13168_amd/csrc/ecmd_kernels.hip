@@ -462,8 +462,9 @@ size_t eval_lds_bytes(int ring_px) {
 // items from the queue until it is empty.  For each item it clears its LDS
 // tile, bins the tile's events (point: one increment per event, interval:
 // one per pixel of the walk) with LDS atomic adds that return nothing, then
-// sums the squares of the tile's counters in one 16-byte-wide pass and
-// removes the border counters' share.
+// removes the border counters' share and sums the squares of the tile's
+// counters in one 16-byte-wide pass that also zeroes them for the next
+// hypothesis.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
@@ -480,6 +481,12 @@ __global__ __launch_bounds__(NT) void k_eval(
     if (blockIdx.x == 0 && tid < kXcd && q_reset) {
         q_reset[tid].n_items = 0;
         q_reset[tid].next = 0;
+    }
+    {  // every counter of the tile region starts at zero and is zeroed again
+       // by the pass that sums each hypothesis's squares
+        uint4* const t4 = reinterpret_cast<uint4*>(tile);
+        const int n4 = eval_counter_words(g.ring_px) >> 2;
+        for (int i = tid; i < n4; i += NT) t4[i] = make_uint4(0u, 0u, 0u, 0u);
     }
     const int home = blockIdx.x % kXcd;
     int qi = 0;  // queues tried so far, starting at this XCD's own (thread 0 only)
@@ -531,13 +538,6 @@ __global__ __launch_bounds__(NT) void k_eval(
       for (int gk = 0; gk < item.cnt; ++gk) {
         const int wh = w * HS + act[w * HS + item.r0 + gk];
         const Hyp hp = hyps[wh];
-
-        {  // clear the counters, 16 bytes per store
-            uint4* const t4 = reinterpret_cast<uint4*>(tile);
-            const int n4 = (ncnt + 3) >> 2;
-            for (int i = tid; i < n4; i += NT) t4[i] = make_uint4(0u, 0u, 0u, 0u);
-        }
-        __syncthreads();
 
         unsigned long long nlow = 0;
         unsigned visits = 0;  // increments by this thread: one per event, plus walk steps
@@ -614,21 +614,13 @@ __global__ __launch_bounds__(NT) void k_eval(
             visits += acc.visits;
             nlow = nlow32;
         }
-        // Sum of squares over the whole counter region, 16 bytes per read,
-        // then the border counters' squares and counts removed.  Each thread
-        // takes some counters (its own sums may wrap; the workgroup's totals
-        // are exact).
+        // The border counters' squares and counts are removed, then the sum
+        // of squares is taken over the whole counter region, 16 bytes per
+        // read, and the region is zeroed for the next hypothesis (every
+        // counter is zero between hypotheses).  Each thread takes some
+        // counters (its own sums may wrap; the workgroup's totals are exact).
         __syncthreads();
         unsigned long long sq = 0, hits = visits;
-        {
-            const uint4* const t4 = reinterpret_cast<const uint4*>(tile);
-            const int n4 = (ncnt + 3) >> 2;  // the clear zeroed the rounded-up region
-            for (int i = tid; i < n4; i += NT) {
-                const uint4 v = t4[i];
-                sq += (unsigned long long)v.x * v.x + (unsigned long long)v.y * v.y +
-                      (unsigned long long)v.z * v.z + (unsigned long long)v.w * v.w;
-            }
-        }
         for (int k = tid; k < nring; k += NT) {
             int idx;
             if (k < R.rw) idx = k;                                      // top row
@@ -637,6 +629,25 @@ __global__ __launch_bounds__(NT) void k_eval(
             const unsigned m = tile[idx];
             sq -= (unsigned long long)m * m;
             hits -= m;
+        }
+        if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
+            const long long M = (long long)g.W * g.H;
+            unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
+            for (int k = tid; k < tw * th; k += NT) {
+                const int lx = k % tw, ly = k / tw;
+                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
+            }
+        }
+        __syncthreads();  // every read of single counters is done before the region is zeroed
+        {
+            uint4* const t4 = reinterpret_cast<uint4*>(tile);
+            const int n4 = (ncnt + 3) >> 2;  // the counters lie in the rounded-up region
+            for (int i = tid; i < n4; i += NT) {
+                const uint4 v = t4[i];
+                t4[i] = make_uint4(0u, 0u, 0u, 0u);
+                sq += (unsigned long long)v.x * v.x + (unsigned long long)v.y * v.y +
+                      (unsigned long long)v.z * v.z + (unsigned long long)v.w * v.w;
+            }
         }
         // block reduction of (S, hits, nlow)
         sq = wave_total(sq);
@@ -663,15 +674,9 @@ __global__ __launch_bounds__(NT) void k_eval(
             pt.pad = 0;
             part[(long long)wh * g.T + t] = pt;
         }
-        if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
-            const long long M = (long long)g.W * g.H;
-            unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
-            for (int k = tid; k < tw * th; k += NT) {
-                const int lx = k % tw, ly = k / tw;
-                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
-            }
-        }
-        __syncthreads();  // the tile is cleared again for the next hypothesis
+        // no barrier here: every thread zeroed its counters before the one
+        // above, and thread 0 reads s_red before the next hypothesis's first
+        // barrier, after which s_red is written again
       }
     }
 }
