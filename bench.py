@@ -58,11 +58,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "8db46e307cca69233b8996d30923f4d8e5d4867dd1ac80bd9595762c61308c8e",
+    "sources_sha256": "7098a5caff342d9a052e07791b07f962b136fec5d850cbce78ee8d0fd745e916",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
-    "fetch_kib": 24487.1,
-    "write_kib": 1040.1,
-    "fetch_bytes_per_kib": 1073741824 / 524305.0,
+    "fetch_kib": 24453.7,
+    "write_kib": 1039.7,
+    "fetch_bytes_per_kib": 1073741824 / 524304.9,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",

@@ -76,6 +76,17 @@ __device__ __forceinline__ unsigned long long dpp_add(unsigned long long v) {
     return v + (((unsigned long long)hi << 32) | lo);
 }
 
+// The same for a 32-bit value whose wave total fits 32 bits.
+__device__ __forceinline__ unsigned wave_total32(unsigned v) {
+    v += __builtin_amdgcn_update_dpp(0u, v, 0xB1, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x4E, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x141, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x140, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);
+    return v;
+}
+
 // Sum over the 64 lanes of a wave in registers (no LDS): quad swaps, half-row
 // and row mirrors give every lane its row's sum; the two row broadcasts then
 // carry rows 0-2 into row 3.  The total is valid in lane 63 (all lanes active).
@@ -652,7 +663,8 @@ __global__ __launch_bounds__(NT) void k_eval(
         // block reduction of (S, hits, nlow)
         sq = wave_total(sq);
         hits = wave_total(hits);
-        nlow = wave_total(nlow);
+        // N_low counts owned events (fewer than 2^28 per segment); points have none
+        if (hp.kind != HYP_POINT) nlow = wave_total32((unsigned)nlow);
         const int wave = tid >> 6, lane = tid & 63;
         if (lane == 63) {
             s_red[wave] = sq;
