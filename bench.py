@@ -58,7 +58,7 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "7098a5caff342d9a052e07791b07f962b136fec5d850cbce78ee8d0fd745e916",
+    "sources_sha256": "feaa87be2ad2fddde25ad0d2f1f0cb6a98e66ca4acd094fd3dee36b06076440c",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
     "fetch_kib": 24453.7,
     "write_kib": 1039.7,

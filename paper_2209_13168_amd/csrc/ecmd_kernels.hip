@@ -469,13 +469,13 @@ size_t eval_lds_bytes(int ring_px) {
     return (size_t)eval_counter_words(ring_px) * 4 + 3 * kEvalWaves * 8 + 4 * (1 + kXcd);
 }
 
-// Persistent evaluation kernel: each workgroup takes (hypothesis, tile)
-// items from the queue until it is empty.  For each item it clears its LDS
-// tile, bins the tile's events (point: one increment per event, interval:
-// one per pixel of the walk) with LDS atomic adds that return nothing, then
-// removes the border counters' share and sums the squares of the tile's
-// counters in one 16-byte-wide pass that also zeroes them for the next
-// hypothesis.
+// Persistent evaluation kernel: each workgroup takes work items (a window's
+// tile segment and one or more hypotheses) from the queue until it is
+// empty.  For each hypothesis it bins the tile's events in LDS (point: one
+// increment per event, interval: one per pixel of the walk) with atomic adds
+// that return nothing, then removes the border counters' share and sums the
+// squares of the tile's counters in one 16-byte-wide pass that also zeroes
+// them for the next hypothesis (the tile region is cleared once, at start).
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
