@@ -58,7 +58,7 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "feaa87be2ad2fddde25ad0d2f1f0cb6a98e66ca4acd094fd3dee36b06076440c",
+    "sources_sha256": "8e1785769dc120bbf3b11ffb6ffeb316920b40a8dd1689b3bd98a6fc171f5aa7",
     "workload": {"config": "c2", "windows": 32, "frontier_batch": 96},
     "fetch_kib": 24453.7,
     "write_kib": 1039.7,

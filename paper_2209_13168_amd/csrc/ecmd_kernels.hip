@@ -399,13 +399,13 @@ __device__ __forceinline__ unsigned* ring_at(unsigned* org, const Ring& R, int k
     return org + mad24(ky, R.rw, kx);
 }
 
-__device__ __forceinline__ void lds_inc(unsigned* p, WalkAcc&) {
+__device__ __forceinline__ void lds_inc(unsigned* p) {
     atomicAdd(p, 1u);  // the old count is not used: no wait for it
 }
 
-__device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py, WalkAcc& acc) {
+__device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, int py) {
     const int cx = clampi(px, R.xlo, R.vxhi), cy = clampi(py, R.ylo, R.vyhi);
-    lds_inc(ring_at(org, R, cx, cy), acc);
+    lds_inc(ring_at(org, R, cx, cy));
 }
 
 __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, int ky, int kxb,
@@ -430,13 +430,13 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
             const double e = ex - ey;
             const bool lo = e < -thr, hi = e > thr;
             if (!lo && !hi) {  // the ray passes near the corner: both side pixels
-                tile_add(org, R, kx + sx, ky, acc);
-                tile_add(org, R, kx, ky + sy, acc);
+                tile_add(org, R, kx + sx, ky);
+                tile_add(org, R, kx, ky + sy);
                 acc.visits += 1;
             }
             kx += !hi ? sx : 0;
             ky += !lo ? sy : 0;
-            tile_add(org, R, kx, ky, acc);
+            tile_add(org, R, kx, ky);
         } while (kx != kxb && ky != kyb);
     }
     // one coordinate left: a straight run along a row or a column
@@ -444,13 +444,13 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
         const int cy = clampi(ky, R.ylo, R.vyhi);
         do {
             kx += sx;
-            lds_inc(org + mad24(cy, R.rw, clampi(kx, R.xlo, R.vxhi)), acc);
+            lds_inc(org + mad24(cy, R.rw, clampi(kx, R.xlo, R.vxhi)));
         } while (kx != kxb);
     } else {
         const int cx = clampi(kx, R.xlo, R.vxhi);
         while (ky != kyb) {
             ky += sy;
-            lds_inc(org + mad24(clampi(ky, R.ylo, R.vyhi), R.rw, cx), acc);
+            lds_inc(org + mad24(clampi(ky, R.ylo, R.vyhi), R.rw, cx));
         }
     }
 }
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(NT) void k_eval(
                 // both endpoints in the image: neither clamped to -1 (as unsigned, huge) nor to W, H
                 nlow32 += (unsigned)(i < nown) & (unsigned)(umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
                           (unsigned)(umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
-                tile_add(org, R, kxa, kya, acc);
+                tile_add(org, R, kxa, kya);
                 if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
             };
             // two events in flight ahead of the one being binned (the
