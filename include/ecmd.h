@@ -8,7 +8,8 @@
  * (12)-(14)) with the branch and bound of Algorithm 1 and the upper bound of
  * Sec. 4.3 (eqs. (15)-(20)), on the GPU.
  *
- * Fixed readings of the method (identical to the library's CPU reference):
+ * Fixed readings of the method (a separate CPU implementation in the tests
+ * states the same readings independently and checks the results against):
  *   - fp32 warp in this order: per event ax = (x - cx)(tau - t'),
  *     ay = (y - cy)(tau - t'); per hypothesis r = d / (1 - d tau);
  *     xw = fmaf(ax, r, x), yw = fmaf(ay, r, y) (eq. (12));
@@ -92,11 +93,15 @@ typedef struct {
  * Algorithm 1 once the best bound is within gamma of the incumbent in
  * contrast units.  max_nodes > 0 caps node expansions (ECMD_EBUDGET).
  * frontier_batch is the expansion policy: the number of queued nodes
- * expanded together per step, largest bound gap first (1 = best-first, one
- * node per step as in Algorithm 1; k > 1 = the k best nodes, evaluated in
- * one launch; 0 = the context's tuning, 96 by default); the canonical
- * result does not depend on it.  frontier_capacity caps queued nodes per
- * window (0 = 16384). */
+ * expanded together per step.  1 = Algorithm 1's order: the queued node with
+ * the largest bound, ties to the smaller grid index, one per step.  k > 1 =
+ * up to k nodes evaluated in one launch, chosen by bound gap K_bar - K_inc
+ * in power-of-two classes: every node of the larger classes, then nodes of
+ * the class where the count reaches k in queue order (each within a factor
+ * two of the largest gap).  0 = the context's tuning, 96 by default.  The
+ * canonical result does not depend on it.  frontier_capacity caps queued
+ * nodes per window (0 = 16384; a window that needs more stops with
+ * ECMD_EFRONTIER, its incumbent and gap = infinity). */
 typedef struct {
     float d_lo, d_hi, eps;
     float reserved0;
@@ -293,8 +298,10 @@ int ecmd_estimate_stream(ecmd_ctx *ctx, const ecmd_sensor *sensor, const ecmd_ev
  * loop, four per block) replaces the host's polling of the search.
  *   max_windows: B of a launch, 1 .. 65535;
  *   max_steps:   frontier steps per launch, rounded up to a multiple of 4
- *                (0 = 256); each costs two kernel launches, which return
- *                at once for finished windows;
+ *                (0 = 2L + 8 for the grid depth L, e.g. 44 for L = 18; a
+ *                search of F nodes per step usually needs about L steps);
+ *                each costs two kernel launches, which return at once for
+ *                finished windows;
  *   max_events:  events of a launch over all windows, 1 .. 2^40;
  *   max_records: binned event records, guest copies included (0 = the worst
  *                case: max_events times the tiles of one FOE quadrant);

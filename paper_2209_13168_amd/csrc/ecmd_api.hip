@@ -1080,7 +1080,9 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
         return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
     ecmd_plan_limits L2 = *lim;
-    if (L2.max_steps == 0) L2.max_steps = 256;
+    // default: twice the grid depth and eight more (a level-synchronous
+    // search needs about L steps; finished steps still cost two launches)
+    if (L2.max_steps == 0) L2.max_steps = min(2 * L + 8, kMaxSteps);
     L2.max_steps = (L2.max_steps + 3) / 4 * 4;  // whole polling blocks of four steps
     if (L2.max_records == 0) {
         // an event's tiles over any range lie in its FOE quadrant (no event

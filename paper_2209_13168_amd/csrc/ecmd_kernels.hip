@@ -1055,19 +1055,24 @@ __global__ __launch_bounds__(NTF) void k_frontier(
     }
     __syncthreads();
 
-    // (3) which queued nodes can still improve; histogram of their gap sizes
+    // (3) which queued nodes can still improve; histogram of their gap
+    // sizes; the node Algorithm 1 would pop next (largest bound, ties to the
+    // smaller grid index; queued intervals are disjoint, so ja names it)
     i128 best_gap = -1;
+    unsigned best_ja = 0xFFFFFFFFu;
     for (int i = tid; i < n; i += NTF) {
         const Node nd = fr[i];
         const i128 k = mk128(nd.khi, nd.klo);
         if (improvable(k, nd.ja, Kinc, jinc)) {
             const i128 gap = k - Kinc;
             atomicAdd(&s_hist[bitlen128(gap)], 1);
-            if (gap > best_gap) best_gap = gap;
+            if (gap > best_gap || (gap == best_gap && nd.ja < best_ja)) {
+                best_gap = gap;
+                best_ja = nd.ja;
+            }
         }
     }
-    unsigned jdummy = 0;
-    block_argmax(best_gap, jdummy, s_hi, s_lo, s_j);
+    block_argmax(best_gap, best_ja, s_hi, s_lo, s_j);
     // the gap classes from the largest down, one thread each: `before` =
     // improvable nodes in larger classes, n_keep = all of them
     const int hb = tid < 130 ? s_hist[129 - tid] : 0;
@@ -1130,7 +1135,11 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         return;
     }
 
-    // (4) split the queue into the nodes expanded now and the rest (in place)
+    // (4) split the queue into the nodes expanded now and the rest (in
+    // place).  One node: Algorithm 1's pop, the best node found above.
+    // More: every node of the larger gap classes and the first `quota`
+    // of class b* in queue order.
+    const bool pop_one = s_take == 1;
     int out = 0, nsel = 0, inb = 0;
     for (int base = 0; base < n; base += NTF) {
         const int i = base + tid;
@@ -1140,10 +1149,15 @@ __global__ __launch_bounds__(NTF) void k_frontier(
             nd = fr[i];
             const i128 k = mk128(nd.khi, nd.klo);
             if (improvable(k, nd.ja, Kinc, jinc)) {
-                const int b = bitlen128(k - Kinc);
-                big = b > s_bstar;
-                cand = b == s_bstar;
-                keep = !big && !cand;
+                if (pop_one) {
+                    big = nd.ja == best_ja;
+                    keep = !big;
+                } else {
+                    const int b = bitlen128(k - Kinc);
+                    big = b > s_bstar;
+                    cand = b == s_bstar;
+                    keep = !big && !cand;
+                }
             }
         }
         int tot_c;

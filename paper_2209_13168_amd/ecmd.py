@@ -10,7 +10,6 @@ call uses one kind for all its arrays.  The library must have been built
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 from dataclasses import dataclass, fields
 from typing import Optional, Sequence
@@ -645,7 +644,3 @@ def _empty_like(ref, n: int, dtype):
 
 def sensor(width: int, height: int, foe: Sequence[float]) -> Sensor:
     return Sensor(int(width), int(height), float(foe[0]), float(foe[1]))
-
-
-def key(M: int, S: int, N: int) -> int:
-    return int(M) * int(S) - int(N) * int(N)

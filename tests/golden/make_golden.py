@@ -17,9 +17,11 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 # (config, window index): the smallest and a large window of the 640x480
-# batch, the smallest windows of the 1280x720 batch (with hot pixels), and
+# batch, the three smallest and the three largest windows of the 1280x720
+# batch (with hot pixels; 4.8-4.9M events plus the hot pixels' ~230k), and
 # extra 346x260 windows.
 CASES = [("c3", 56), ("c3", 9), ("c3", 11), ("c5", 179), ("c5", 110), ("c5", 138),
+         ("c5", 64), ("c5", 2), ("c5", 95),
          ("c2", 2), ("c2", 3), ("c2", 4), ("c2", 5)]
 
 

@@ -85,3 +85,45 @@ def test_full_640x480_batch(ctx, orc):
 
 def test_full_1280x720_batch_with_hot_pixels(ctx, orc):
     _check(ctx, orc, "c5", 256, 3)
+
+
+def test_images_on_the_1280x720_tiling_with_hot_pixels(ctx, orc):
+    """Point and upper-bound images (eqs. (13) and (17)) of a 1280x720 window
+    with its hot pixels, at the default tiling of that sensor (24 tiles,
+    1024-thread evaluation workgroups, guest copies across the cuts inside
+    each FOE quadrant): every cell, S, N and N_low equal the oracle's, at
+    grid intervals of every depth from the root to a singleton."""
+    from paper_2209_13168_amd import ecmd
+    from synth import config_windows
+
+    w = config_windows("c5", [7], n_events=150_000)[0]
+    s = w.spec
+    assert w.n_hot > 100_000
+    sen = ecmd.sensor(s.width, s.height, s.foe)
+    p = ecmd.plan(sen, s.d_lo, s.d_hi, s.eps)
+    assert (p["segments"], p["eval_threads"]) == (24, 1024)
+    ev = orc.Events.of_window(w)
+    M = s.width * s.height
+    rng = np.random.default_rng(11)
+    ds = np.concatenate([[0.0, np.float32(s.d_true), np.float32(0.003)],
+                         rng.uniform(s.d_lo, s.d_hi, 3)]).astype(np.float32)
+    S, N, img = ctx.probe_point(sen, w.x, w.y, w.t_rel, s.tau, ds, want_image=True)
+    for k, d in enumerate(ds):
+        So, No, Ho = orc.point(ev, float(d), want_image=True)
+        assert (int(S[k]), int(N[k])) == (So, No), (k, d)
+        assert np.array_equal(img[k * M:(k + 1) * M], Ho), (k, d)
+    L = orc.depth(s.d_lo, s.d_hi, s.eps)
+    da, db = [], []
+    for depth in (0, 1, 3, 6, 10, 14, L - 1):
+        size = 1 << (L - depth)
+        ja = int(rng.integers(0, 1 << depth)) * size
+        da.append(orc.grid_d(s.d_lo, s.d_hi, L, ja))
+        db.append(orc.grid_d(s.d_lo, s.d_hi, L, ja + size))
+    da.append(float(ds[1]))
+    db.append(float(ds[1]))  # singleton
+    da, db = np.array(da, np.float32), np.array(db, np.float32)
+    Sb, Nl, img = ctx.probe_bound(sen, w.x, w.y, w.t_rel, s.tau, s.d_lo, s.d_hi, da, db, want_image=True)
+    for k in range(da.size):
+        So, No, Ho = orc.bound(ev, float(da[k]), float(db[k]), want_image=True)
+        assert (int(Sb[k]), int(Nl[k])) == (So, No), (k, da[k], db[k])
+        assert np.array_equal(img[k * M:(k + 1) * M], Ho), (k, da[k], db[k])
