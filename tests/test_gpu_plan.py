@@ -72,7 +72,9 @@ def test_plan_equals_the_synchronous_call_and_the_oracle(ctx, orc):
     x, y, t, off, tau = pack_batch(wins)
     sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, 1e-4)
     plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, 1e-4, max_windows=8, max_events=int(off[-1]) + 100)
-    assert plan.limits["max_steps"] == 256 and plan.limits["max_records"] >= int(off[-1])
+    # default step count: twice the grid depth (L = 14 at eps 1e-4 over [0, 1]) and eight more, in whole
+    # blocks of four
+    assert plan.limits["max_steps"] == 36 and plan.limits["max_records"] >= int(off[-1])
     got = _launch(plan, *_dev(x, y, t, off, tau))
     for i, w in enumerate(wins):
         _same(got[i], sync[i])
