@@ -348,6 +348,38 @@ int ecmd_plan_launch(ecmd_batch_plan *plan, const float *x, const float *y, cons
 /* Free the plan (waits for the context's stream first). */
 void ecmd_plan_destroy(ecmd_batch_plan *plan);
 
+/* ------------------------------------------------ allocation-free search */
+
+/* Bytes of device memory the library holds on each device it runs on, for
+ * ecmd_estimate_divergence_batched_noalloc (until the process ends). */
+#define ECMD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+
+/* For callers that cannot allocate device memory: code under stream or
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  The
+ * batched search of ecmd_plan_launch without a plan: every device buffer
+ * it needs comes from one static array of ECMD_NOALLOC_SCRATCH_BYTES on the
+ * context's device, so the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine) and only enqueues kernels on the context's
+ * stream; ecmd_ctx_create looks the array's address up on its device.
+ * Arguments and results are those of ecmd_plan_launch for a plan with
+ * limits {max_windows = B, max_steps = 0, max_events, max_records = 0,
+ * polarity = 0}: every array a device pointer on the context's device, out
+ * in device memory or pinned host memory, written when the stream gets
+ * there, with the plan's per-window statuses.  Returns ECMD_ENOMEM, with a
+ * message and nothing launched, when the buffers for B windows of up to
+ * max_events events exceed the array (the event store takes 16 bytes per
+ * event and image tile of its FOE quadrant, the frontier 32 bytes per node
+ * of frontier_capacity per window); ECMD_EINVAL for the plan's argument
+ * errors.  The array keeps the last call's contents (each call clears what
+ * it reads before writing it); calls that overlap on one device (other
+ * streams, threads or contexts) race. */
+int ecmd_estimate_divergence_batched_noalloc(ecmd_ctx *ctx, const ecmd_sensor *sensor,
+                                             const ecmd_search *search, const float *x,
+                                             const float *y, const float *t_rel,
+                                             const int64_t *offsets, const float *tau, int32_t B,
+                                             int64_t max_events, const float *d_seeds,
+                                             ecmd_result *out);
+
 /* -------------------------------------------------------------- probes */
 
 /* Pixel index ky*W + kx of every event at divergence d (-1 = outside),

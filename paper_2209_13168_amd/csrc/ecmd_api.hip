@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -752,6 +753,51 @@ static int batched_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, 
 
 // ------------------------------------------------------- asynchronous plan
 
+// The shape of batched searches up to fixed limits: tiling, search
+// parameters and launch sizes (set once, by ecmd_plan_create or by each
+// allocation-free call).
+struct PlanShape {
+    ecmd_plan_limits lim{};
+    Geometry g{};
+    Search sp{};       // G is set per launch
+    int nblk_max = 0;  // prep workgroups of the largest launch
+    int qcap = 0;
+    size_t lds = 0;
+    int nt = 0;        // threads per evaluation workgroup
+    int nb = 0;
+};
+
+// Device buffers of a plan, in this order.
+enum PlanBuf {
+    PB_WP, PB_BLK, PB_CNT, PB_SEG_OFF, PB_SEG_OWN, PB_CURSOR, PB_EV, PB_WERR, PB_WSTAT, PB_STATE, PB_FRONT, PB_SEL,
+    PB_HYPS, PB_ACT, PB_ITEMS, PB_QUEUES, PB_PART, PB_NACTIVE, PB_COUNT
+};
+
+// Bytes of each device buffer for the shape's limits.
+static void plan_sizes(const PlanShape& sh, size_t* bytes) {
+    const int Bm = sh.lim.max_windows, T = sh.g.T;
+    const Search& sp = sh.sp;
+    const size_t nctr = prep_counters(Bm, T);
+    bytes[PB_WP] = sizeof(WinParam) * Bm;
+    bytes[PB_BLK] = sizeof(int) * (Bm + 1);
+    bytes[PB_CNT] = sizeof(int) * nctr;
+    bytes[PB_SEG_OFF] = sizeof(long long) * ((size_t)Bm * T + 1);
+    bytes[PB_SEG_OWN] = sizeof(int) * (size_t)Bm * T;
+    bytes[PB_CURSOR] = sizeof(unsigned long long) * nctr;
+    bytes[PB_EV] = sizeof(float4) * (size_t)(sh.lim.max_records + kEvalPad);  // padded as in the synchronous call
+    bytes[PB_WERR] = sizeof(int) * Bm;
+    bytes[PB_WSTAT] = sizeof(int) * Bm;
+    bytes[PB_STATE] = sizeof(WinState) * Bm;
+    bytes[PB_FRONT] = sizeof(Node) * (size_t)Bm * sp.CAP;
+    bytes[PB_SEL] = sizeof(Sel) * (size_t)Bm * sp.F;
+    bytes[PB_HYPS] = sizeof(Hyp) * (size_t)Bm * sp.HS;
+    bytes[PB_ACT] = sizeof(int) * (size_t)Bm * sp.HS;
+    bytes[PB_ITEMS] = sizeof(Item) * (size_t)kXcd * sh.qcap;
+    bytes[PB_QUEUES] = sizeof(Queue) * 2 * kXcd;
+    bytes[PB_PART] = sizeof(Part) * (size_t)Bm * sp.HS * T;
+    bytes[PB_NACTIVE] = sizeof(int);
+}
+
 // Device buffers of batched searches up to fixed limits; a launch only
 // enqueues kernels (no allocation, host copy or wait), so it can be
 // captured into a graph and replayed.
@@ -759,40 +805,163 @@ struct ecmd_batch_plan {
     ecmd_ctx* ctx = nullptr;  // NULL once the context is destroyed
     ecmd_sensor sensor{};
     ecmd_search search{};
-    ecmd_plan_limits lim{};
-    Geometry g{};
-    Search sp{};      // G is set per launch
-    int nblk_max = 0;  // prep workgroups of the largest launch
-    int qcap = 0;
-    size_t lds = 0;
-    int nt = 0;        // threads per evaluation workgroup
-    int nb = 0;
-    DevBuf wp, blk, cnt, seg_off, seg_own, cursor, ev, werr, wstat, state, front, sel, hyps, act, items, queues, part,
-        n_active;
+    PlanShape sh;
+    DevBuf buf[PB_COUNT];
 };
 
 static void plan_release(ecmd_batch_plan* p) {
-    DevBuf* bufs[] = {&p->wp,    &p->blk,  &p->cnt,  &p->seg_off, &p->seg_own, &p->cursor, &p->ev,
-                      &p->werr,  &p->wstat, &p->state, &p->front,  &p->sel,     &p->hyps,   &p->act,
-                      &p->items, &p->queues, &p->part, &p->n_active};
-    for (DevBuf* b : bufs) b->release();
+    for (DevBuf& b : p->buf) b.release();
 }
 
+// Validates the sensor, search and limits and fills the shape (zero limits
+// replaced by the values used); sets the context's evaluation kernel up.
+static int plan_shape(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* search,
+                      const ecmd_plan_limits* lim, PlanShape& sh) {
+    int rc = check_sensor(c, sensor);
+    if (rc) return rc;
+    int L = 0;
+    rc = check_search(c, search, &L);
+    if (rc) return rc;
+    if (!lim) return fail(c, ECMD_EINVAL, "limits is NULL");
+    if (lim->max_windows < 1 || lim->max_windows > 65535)
+        return fail(c, ECMD_EINVAL, "max_windows = %d out of range 1 .. 65535", lim->max_windows);
+    if (lim->max_events < 1 || lim->max_events > (1ll << 40))
+        return fail(c, ECMD_EINVAL, "max_events = %lld out of range 1 .. 2^40", (long long)lim->max_events);
+    if (lim->max_steps < 0 || lim->max_steps > kMaxSteps)
+        return fail(c, ECMD_EINVAL, "max_steps = %d out of range 0 .. %d", lim->max_steps, kMaxSteps);
+    if (lim->max_records < 0) return fail(c, ECMD_EINVAL, "max_records must be >= 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int W = sensor->width, H = sensor->height;
+    const int npol = lim->polarity ? 2 : 1;
+    Geometry& g = sh.g;
+    int nt = 0, budget = 0;
+    if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
+        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
+    ecmd_plan_limits L2 = *lim;
+    // default: twice the grid depth and eight more (a level-synchronous
+    // search needs about L steps; finished steps still cost two launches)
+    if (L2.max_steps == 0) L2.max_steps = min(2 * L + 8, kMaxSteps);
+    L2.max_steps = (L2.max_steps + 3) / 4 * 4;  // whole polling blocks of four steps
+    if (L2.max_records == 0) {
+        // an event's tiles over any range lie in its FOE quadrant (no event
+        // crosses an FOE line), so it has at most that many copies
+        const bool xcut = sensor->foe_x == floorf(sensor->foe_x) && sensor->foe_x > 0.0f && sensor->foe_x < (float)W;
+        const bool ycut = sensor->foe_y == floorf(sensor->foe_y) && sensor->foe_y > 0.0f && sensor->foe_y < (float)H;
+        const long long per = (long long)(xcut ? g.ntx / 2 : g.ntx) * (ycut ? g.nty / 2 : g.nty);
+        L2.max_records = L2.max_events * per;
+    }
+    sh.lim = L2;
+    Search& sp = sh.sp;
+    sp.d_lo = search->d_lo;
+    sp.d_hi = search->d_hi;
+    sp.L = L;
+    sp.F = search->frontier_batch > 0 ? search->frontier_batch
+                                      : (c->tune.frontier_batch > 0 ? c->tune.frontier_batch : kDefaultF);
+    sp.CAP = search->frontier_capacity > 0 ? search->frontier_capacity : kDefaultCap;
+    sp.HS = 3 * sp.F;
+    sp.max_nodes = search->max_nodes;
+    const long long M = (long long)W * H * npol;
+    sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
+    sp.M = M;
+    sp.G = 1;
+    sp.B = 1;
+    sp.gslots = 0;
+    const int Bm = L2.max_windows;
+    sh.nblk_max = (int)((L2.max_events + kChunk - 1) / kChunk) + Bm;
+    sh.qcap = ((Bm + kXcd - 1) / kXcd) * sp.HS * g.T;
+    sh.lds = eval_lds_bytes(g.ring_px);
+    sh.nt = nt;
+    HIPCHK(c, eval_setup(c, sh.lds, sh.nt, &sh.nb));
+    return ECMD_OK;
+}
 
 // The prep of a launch: clear the counters, count + scan, scatter (at most
-// p->lim.max_records records).
-static hipError_t plan_prep(ecmd_batch_plan* p, hipStream_t s, const float* x, const float* y, const float* t,
-                            const signed char* pol, const long long* off, int B) {
-    const Geometry& g = p->g;
-    hipError_t e = launch_fill_u32(s, p->cnt.as<unsigned>(), (long long)prep_counters(B, g.T), 0u);
+// max_records records).
+static hipError_t plan_prep(const PlanShape& sh, void* const* b, hipStream_t s, const float* x, const float* y,
+                            const float* t, const signed char* pol, const long long* off, int B) {
+    const Geometry& g = sh.g;
+    hipError_t e = launch_fill_u32(s, (unsigned*)b[PB_CNT], (long long)prep_counters(B, g.T), 0u);
     if (e != hipSuccess) return e;
-    e = launch_prep(s, 0, g, x, y, t, pol, off, p->wp.as<WinParam>(), B, p->blk.as<int>(), p->nblk_max, kChunk,
-                    p->cnt.as<int>(), p->seg_off.as<long long>(), p->seg_own.as<int>(),
-                    p->cursor.as<unsigned long long>(), nullptr, p->werr.as<int>(), -1);
+    e = launch_prep(s, 0, g, x, y, t, pol, off, (const WinParam*)b[PB_WP], B, (const int*)b[PB_BLK], sh.nblk_max,
+                    kChunk, (int*)b[PB_CNT], (long long*)b[PB_SEG_OFF], (int*)b[PB_SEG_OWN],
+                    (unsigned long long*)b[PB_CURSOR], nullptr, (int*)b[PB_WERR], -1);
     if (e != hipSuccess) return e;
-    return launch_prep(s, 1, g, x, y, t, pol, off, p->wp.as<WinParam>(), B, p->blk.as<int>(), p->nblk_max, kChunk,
-                       nullptr, p->seg_off.as<long long>(), nullptr, p->cursor.as<unsigned long long>(),
-                       p->ev.as<float4>(), nullptr, p->lim.max_records);
+    return launch_prep(s, 1, g, x, y, t, pol, off, (const WinParam*)b[PB_WP], B, (const int*)b[PB_BLK], sh.nblk_max,
+                       kChunk, nullptr, (long long*)b[PB_SEG_OFF], nullptr, (unsigned long long*)b[PB_CURSOR],
+                       (float4*)b[PB_EV], nullptr, sh.lim.max_records);
+}
+
+// Enqueues a whole batched search of B windows on the context's stream with
+// the plan buffers b (device checks, prep, a fixed number of steps, results).
+static int plan_enqueue(ecmd_ctx* c, const PlanShape& sh, void* const* b, const float* x, const float* y,
+                        const float* t_rel, const int8_t* polarity, const int64_t* offsets, const float* tau, int B,
+                        const float* d_seeds, ecmd_result* out) {
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const Geometry& g = sh.g;
+    const int T = g.T;
+    Search sp = sh.sp;
+    set_groups(c, B, sp, T);
+    const long long* off = (const long long*)offsets;
+    const signed char* pol = (const signed char*)polarity;
+    WinParam* wp = (WinParam*)b[PB_WP];
+    WinState* st = (WinState*)b[PB_STATE];
+    Sel* sel = (Sel*)b[PB_SEL];
+    Hyp* hyps = (Hyp*)b[PB_HYPS];
+    int* act = (int*)b[PB_ACT];
+    Item* items = (Item*)b[PB_ITEMS];
+    Queue* q = (Queue*)b[PB_QUEUES];
+    Part* part = (Part*)b[PB_PART];
+    long long* seg_off = (long long*)b[PB_SEG_OFF];
+    HIPCHK(c, launch_plan_check(s, off, tau, B, sp.d_hi, g.W, g.H, sh.lim.max_events, kChunk, (int*)b[PB_WSTAT],
+                                (int*)b[PB_WERR], (int*)b[PB_BLK], q, (int*)b[PB_NACTIVE]));
+    HIPCHK(c, launch_winparam(s, g, tau, off, B, sp.d_lo, sp.d_hi, wp));
+    HIPCHK(c, plan_prep(sh, b, s, x, y, t_rel, pol, off, B));
+    HIPCHK(c, launch_init(s, sp, wp, d_seeds, B, st, sel, hyps, act, items, sh.qcap, &q[0], T, seg_off,
+                          InitCheck{(const int*)b[PB_WSTAT], (const int*)b[PB_WERR], (long long)sh.lim.max_records}));
+    for (int step = 0; step < sh.lim.max_steps; step += 4) {
+        for (int k = 0; k < 4; ++k) {
+            const int parity = k & 1;
+            HIPCHK(c, launch_eval(s, g, sh.nb, sh.nt, sh.lds, (const float4*)b[PB_EV], seg_off,
+                                  (const int*)b[PB_SEG_OWN], hyps, act, items, sh.qcap, &q[parity * kXcd],
+                                  &q[(1 - parity) * kXcd], part, sp.HS, nullptr));
+            HIPCHK(c, launch_frontier(s, sp, wp, B, T, seg_off, st, (Node*)b[PB_FRONT], sel, hyps, act, part, items,
+                                      sh.qcap, &q[(1 - parity) * kXcd], (int*)b[PB_NACTIVE]));
+        }
+        // bin again with the live ranges, at the synchronous call's polling
+        // points (unconditionally: the host does not see the copy count)
+        if (step / 4 < kMaxRebins && step + 4 < sh.lim.max_steps) {
+            HIPCHK(c, launch_live_range(s, sp, st, (const Node*)b[PB_FRONT], sel, wp, B));
+            HIPCHK(c, plan_prep(sh, b, s, x, y, t_rel, pol, off, B));
+        }
+    }
+    HIPCHK(c, launch_plan_results(s, sp, B, st, off, tau, out));
+    return ECMD_OK;
+}
+
+// The allocation-free batched search takes its device buffers from this
+// array (each device that loads the library holds one copy until the
+// process ends).  Its device address is looked up once per device when a
+// context is created on it, and only that address is used by host code.
+// Calls on one device share the array: calls that overlap (on different
+// streams or threads) race.
+constexpr size_t kScratchBytes = (size_t)ECMD_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+static void* g_scratch_at[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+// The scratch array's device address on `device` (the current device),
+// looked up on first use.  NULL when the lookup fails.
+static void* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_at[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_at[device] = ptr;
+    }
+    return g_scratch_at[device];
 }
 
 // ------------------------------------------------------------------ ABI
@@ -824,6 +993,12 @@ int ecmd_ctx_create(ecmd_ctx** out, int device, void* hip_stream) {
     }
     c->num_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
+    // the allocation-free call's scratch on this device (device current)
+    if (device < kScratchDevices && !scratch_address(device)) {
+        if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+        delete c;
+        return ECMD_EDEVICE;
+    }
     *out = c;
     return ECMD_OK;
 }
@@ -1059,97 +1234,26 @@ int ecmd_plan_create(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* 
     if (!c || !out) return ECMD_EINVAL;
     c->err.clear();
     *out = nullptr;
-    int rc = check_sensor(c, sensor);
+    PlanShape sh;
+    int rc = plan_shape(c, sensor, search, lim, sh);
     if (rc) return rc;
-    int L = 0;
-    rc = check_search(c, search, &L);
-    if (rc) return rc;
-    if (!lim) return fail(c, ECMD_EINVAL, "limits is NULL");
-    if (lim->max_windows < 1 || lim->max_windows > 65535)
-        return fail(c, ECMD_EINVAL, "max_windows = %d out of range 1 .. 65535", lim->max_windows);
-    if (lim->max_events < 1 || lim->max_events > (1ll << 40))
-        return fail(c, ECMD_EINVAL, "max_events = %lld out of range 1 .. 2^40", (long long)lim->max_events);
-    if (lim->max_steps < 0 || lim->max_steps > kMaxSteps)
-        return fail(c, ECMD_EINVAL, "max_steps = %d out of range 0 .. %d", lim->max_steps, kMaxSteps);
-    if (lim->max_records < 0) return fail(c, ECMD_EINVAL, "max_records must be >= 0");
-    HIPCHK(c, hipSetDevice(c->device));
-    const int W = sensor->width, H = sensor->height;
-    const int npol = lim->polarity ? 2 : 1;
-    Geometry g;
-    int nt = 0, budget = 0;
-    if (!choose_tiling(c->max_lds, c->tune, W, H, sensor->foe_x, sensor->foe_y, npol, g, nt, budget))
-        return fail(c, ECMD_EINVAL, "sensor %dx%d needs more than %d tiles", W, H, kMaxTiles / npol);
-    ecmd_plan_limits L2 = *lim;
-    // default: twice the grid depth and eight more (a level-synchronous
-    // search needs about L steps; finished steps still cost two launches)
-    if (L2.max_steps == 0) L2.max_steps = min(2 * L + 8, kMaxSteps);
-    L2.max_steps = (L2.max_steps + 3) / 4 * 4;  // whole polling blocks of four steps
-    if (L2.max_records == 0) {
-        // an event's tiles over any range lie in its FOE quadrant (no event
-        // crosses an FOE line), so it has at most that many copies
-        const bool xcut = sensor->foe_x == floorf(sensor->foe_x) && sensor->foe_x > 0.0f && sensor->foe_x < (float)W;
-        const bool ycut = sensor->foe_y == floorf(sensor->foe_y) && sensor->foe_y > 0.0f && sensor->foe_y < (float)H;
-        const long long per = (long long)(xcut ? g.ntx / 2 : g.ntx) * (ycut ? g.nty / 2 : g.nty);
-        L2.max_records = L2.max_events * per;
-    }
     ecmd_batch_plan* p = new (std::nothrow) ecmd_batch_plan();
     if (!p) return fail(c, ECMD_ENOMEM, "host allocation failed");
     p->ctx = c;
     p->sensor = *sensor;
     p->search = *search;
-    p->lim = L2;
-    p->g = g;
-    Search& sp = p->sp;
-    sp.d_lo = search->d_lo;
-    sp.d_hi = search->d_hi;
-    sp.L = L;
-    sp.F = search->frontier_batch > 0 ? search->frontier_batch
-                                      : (c->tune.frontier_batch > 0 ? c->tune.frontier_batch : kDefaultF);
-    sp.CAP = search->frontier_capacity > 0 ? search->frontier_capacity : kDefaultCap;
-    sp.HS = 3 * sp.F;
-    sp.max_nodes = search->max_nodes;
-    const long long M = (long long)W * H * npol;
-    sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
-    sp.M = M;
-    sp.G = 1;
-    sp.B = 1;
-    sp.gslots = 0;
-    const int Bm = L2.max_windows, T = g.T;
-    p->nblk_max = (int)((L2.max_events + kChunk - 1) / kChunk) + Bm;
-    p->qcap = ((Bm + kXcd - 1) / kXcd) * sp.HS * T;
-    const size_t nctr = prep_counters(Bm, T);
+    p->sh = sh;
+    size_t bytes[PB_COUNT];
+    plan_sizes(sh, bytes);
     hipError_t e = hipSuccess;
-    auto get = [&](DevBuf& b, size_t bytes) {
-        if (e == hipSuccess) e = b.ensure(bytes);
-    };
-    get(p->wp, sizeof(WinParam) * Bm);
-    get(p->blk, sizeof(int) * (Bm + 1));
-    get(p->cnt, sizeof(int) * nctr);
-    get(p->seg_off, sizeof(long long) * ((size_t)Bm * T + 1));
-    get(p->seg_own, sizeof(int) * (size_t)Bm * T);
-    get(p->cursor, sizeof(unsigned long long) * nctr);
-    get(p->ev, sizeof(float4) * (size_t)(L2.max_records + kEvalPad));  // padded as in the synchronous call
-    get(p->werr, sizeof(int) * Bm);
-    get(p->wstat, sizeof(int) * Bm);
-    get(p->state, sizeof(WinState) * Bm);
-    get(p->front, sizeof(Node) * (size_t)Bm * sp.CAP);
-    get(p->sel, sizeof(Sel) * (size_t)Bm * sp.F);
-    get(p->hyps, sizeof(Hyp) * (size_t)Bm * sp.HS);
-    get(p->act, sizeof(int) * (size_t)Bm * sp.HS);
-    get(p->items, sizeof(Item) * (size_t)kXcd * p->qcap);
-    get(p->queues, sizeof(Queue) * 2 * kXcd);
-    get(p->part, sizeof(Part) * (size_t)Bm * sp.HS * T);
-    get(p->n_active, sizeof(int));
-    p->lds = eval_lds_bytes(g.ring_px);
-    p->nt = nt;
-    if (e == hipSuccess) e = eval_setup(c, p->lds, p->nt, &p->nb);
+    for (int k = 0; k < PB_COUNT && e == hipSuccess; ++k) e = p->buf[k].ensure(bytes[k]);
     if (e != hipSuccess) {
         plan_release(p);
         delete p;
         HIPCHK(c, e);
     }
     c->plans.push_back(p);
-    *lim = L2;
+    *lim = sh.lim;
     *out = p;
     return ECMD_OK;
 }
@@ -1160,50 +1264,14 @@ int ecmd_plan_launch(ecmd_batch_plan* p, const float* x, const float* y, const f
     ecmd_ctx* c = p->ctx;
     if (!c) return ECMD_EINVAL;  // the context is gone
     c->err.clear();
-    if (B < 1 || B > p->lim.max_windows)
-        return fail(c, ECMD_EINVAL, "B = %d out of range 1 .. %d", B, p->lim.max_windows);
+    if (B < 1 || B > p->sh.lim.max_windows)
+        return fail(c, ECMD_EINVAL, "B = %d out of range 1 .. %d", B, p->sh.lim.max_windows);
     if (!x || !y || !t_rel || !offsets || !tau || !out) return fail(c, ECMD_EINVAL, "NULL array argument");
-    if ((polarity != nullptr) != (p->lim.polarity != 0))
+    if ((polarity != nullptr) != (p->sh.lim.polarity != 0))
         return fail(c, ECMD_EINVAL, "polarity must be given exactly when the plan was created for it");
-    HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = c->stream;
-    const Geometry& g = p->g;
-    const int T = g.T;
-    Search sp = p->sp;
-    set_groups(c, B, sp, T);
-    const long long* off = (const long long*)offsets;
-    const signed char* pol = (const signed char*)polarity;
-    Queue* q = p->queues.as<Queue>();
-    HIPCHK(c, launch_plan_check(s, off, tau, B, sp.d_hi, g.W, g.H, p->lim.max_events, kChunk, p->wstat.as<int>(),
-                                p->werr.as<int>(), p->blk.as<int>(), q, p->n_active.as<int>()));
-    HIPCHK(c, launch_winparam(s, g, tau, off, B, sp.d_lo, sp.d_hi, p->wp.as<WinParam>()));
-    HIPCHK(c, plan_prep(p, s, x, y, t_rel, pol, off, B));
-    HIPCHK(c, launch_init(s, sp, p->wp.as<WinParam>(), d_seeds, B, p->state.as<WinState>(), p->sel.as<Sel>(),
-                          p->hyps.as<Hyp>(), p->act.as<int>(), p->items.as<Item>(), p->qcap, &q[0], T,
-                          p->seg_off.as<long long>(),
-                          InitCheck{p->wstat.as<int>(), p->werr.as<int>(), (long long)p->lim.max_records}));
-    for (int step = 0; step < p->lim.max_steps; step += 4) {
-        for (int k = 0; k < 4; ++k) {
-            const int parity = k & 1;
-            HIPCHK(c, launch_eval(s, g, p->nb, p->nt, p->lds, p->ev.as<float4>(), p->seg_off.as<long long>(),
-                                  p->seg_own.as<int>(), p->hyps.as<Hyp>(), p->act.as<int>(), p->items.as<Item>(),
-                                  p->qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd], p->part.as<Part>(), sp.HS,
-                                  nullptr));
-            HIPCHK(c, launch_frontier(s, sp, p->wp.as<WinParam>(), B, T, p->seg_off.as<long long>(),
-                                      p->state.as<WinState>(), p->front.as<Node>(), p->sel.as<Sel>(),
-                                      p->hyps.as<Hyp>(), p->act.as<int>(), p->part.as<Part>(), p->items.as<Item>(),
-                                      p->qcap, &q[(1 - parity) * kXcd], p->n_active.as<int>()));
-        }
-        // bin again with the live ranges, at the synchronous call's polling
-        // points (unconditionally: the host does not see the copy count)
-        if (step / 4 < kMaxRebins && step + 4 < p->lim.max_steps) {
-            HIPCHK(c, launch_live_range(s, sp, p->state.as<WinState>(), p->front.as<Node>(), p->sel.as<Sel>(),
-                                        p->wp.as<WinParam>(), B));
-            HIPCHK(c, plan_prep(p, s, x, y, t_rel, pol, off, B));
-        }
-    }
-    HIPCHK(c, launch_plan_results(s, sp, B, p->state.as<WinState>(), off, tau, out));
-    return ECMD_OK;
+    void* b[PB_COUNT];
+    for (int k = 0; k < PB_COUNT; ++k) b[k] = p->buf[k].p;
+    return plan_enqueue(c, p->sh, b, x, y, t_rel, polarity, offsets, tau, B, d_seeds, out);
 }
 
 void ecmd_plan_destroy(ecmd_batch_plan* p) {
@@ -1215,6 +1283,38 @@ void ecmd_plan_destroy(ecmd_batch_plan* p) {
         c->plans.erase(std::remove(c->plans.begin(), c->plans.end(), p), c->plans.end());
     }
     delete p;
+}
+
+int ecmd_estimate_divergence_batched_noalloc(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search* search,
+                                             const float* x, const float* y, const float* t_rel,
+                                             const int64_t* offsets, const float* tau, int32_t B, int64_t max_events,
+                                             const float* d_seeds, ecmd_result* out) {
+    if (!c) return ECMD_EINVAL;
+    c->err.clear();
+    if (B < 1 || B > 65535) return fail(c, ECMD_EINVAL, "B = %d out of range 1 .. 65535", B);
+    if (!x || !y || !t_rel || !offsets || !tau || !out) return fail(c, ECMD_EINVAL, "NULL array argument");
+    ecmd_plan_limits lim{};
+    lim.max_windows = B;
+    lim.max_events = max_events;
+    PlanShape sh;
+    int rc = plan_shape(c, sensor, search, &lim, sh);
+    if (rc) return rc;
+    size_t bytes[PB_COUNT];
+    plan_sizes(sh, bytes);
+    void* base = scratch_address(c->device);
+    if (!base) return fail(c, ECMD_EDEVICE, "no scratch address on device %d", c->device);
+    void* b[PB_COUNT];
+    size_t used = 0;
+    for (int k = 0; k < PB_COUNT; ++k) {
+        b[k] = (char*)base + used;
+        used += (bytes[k] + 255) / 256 * 256;  // every buffer on a 256-byte boundary
+    }
+    if (used > kScratchBytes)
+        return fail(c, ECMD_ENOMEM,
+                    "%d windows of up to %lld events need %zu bytes of scratch, more than the %zu the "
+                    "allocation-free call holds",
+                    B, (long long)max_events, used, kScratchBytes);
+    return plan_enqueue(c, sh, b, x, y, t_rel, nullptr, offsets, tau, B, d_seeds, out);
 }
 
 int ecmd_estimate_divergence(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_events* events,

@@ -136,6 +136,8 @@ def _load():
                              C.c_int),
         "ecmd_plan_launch": ([vp, vp, vp, vp, vp, vp, vp, i32, vp, vp], C.c_int),
         "ecmd_plan_destroy": ([vp], None),
+        "ecmd_estimate_divergence_batched_noalloc": ([vp, C.POINTER(Sensor), C.POINTER(SearchS), vp, vp, vp, vp, vp,
+                                                      i32, i64, vp, vp], C.c_int),
         "ecmd_measure_peaks": ([vp, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
         "ecmd_ctx_set_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
         "ecmd_ctx_get_tuning": ([vp, C.POINTER(TuningS)], C.c_int),
@@ -396,6 +398,26 @@ class Context:
         return BatchPlan(self, sensor, _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity),
                          PlanLimitsS(int(max_windows), int(max_steps), int(max_events), int(max_records),
                                      1 if polarity else 0, 0))
+
+    def estimate_batched_noalloc(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
+                                 eps: float, max_events: int, out, gamma: float = 0.0, max_nodes: int = 0,
+                                 frontier_batch: int = 0, frontier_capacity: int = 0, d_seeds=None):
+        """The batched search on the library's static scratch (no device
+        allocation): torch CUDA tensors in, results into ``out`` (a
+        ``BatchPlan.result_buffer``) when the stream reaches them."""
+        a = _Args()
+        B = int(tau.shape[0])
+        args = [a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32), a.ptr(offsets, np.int64),
+                a.ptr(tau, np.float32), B, int(max_events),
+                a.ptr(d_seeds, np.float32) if d_seeds is not None else None]
+        if not a.device:
+            raise TypeError("the allocation-free search takes device arrays")
+        if out.numel() < C.sizeof(ResultS) * B:
+            raise ValueError("result buffer too small")
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        rc = lib().ecmd_estimate_divergence_batched_noalloc(self.h, C.byref(sensor), C.byref(sp), *args,
+                                                            C.c_void_p(out.data_ptr()))
+        self._check(rc)
 
     # -------------------------------------------------------------- probes
     def probe_pixels(self, sensor: Sensor, x, y, t_rel, tau: float, d: float, out=None):
