@@ -101,10 +101,25 @@ typedef struct {
  * two of the largest gap).  0 = the context's tuning, 96 by default.  The
  * canonical result does not depend on it.  frontier_capacity caps queued
  * nodes per window (0 = 16384; a window that needs more stops with
- * ECMD_EFRONTIER, its incumbent and gap = infinity). */
+ * ECMD_EFRONTIER, its incumbent and gap = infinity).
+ *
+ * flags: ECMD_SEARCH_EXACT_BOUNDS computes the bound of eqs. (15)-(20) for
+ * every child interval.  Without it (the default), a child whose decision
+ * cannot depend on its bound's value (gamma = 0, no node budget, and every
+ * node the queue can hold after this step is expanded next) is first given
+ * a cheaper certificate from its endpoints alone: with U the sum over the
+ * owned events with both endpoints in the image of |dkx| + |dky| + 1 (the
+ * walk visits that many distinct image pixels), Cauchy-Schwarz over the M
+ * cells gives M * S_bar >= U^2, so K_bar >= U^2 - N_low^2.  When that
+ * exceeds the incumbent the node is kept, the decision the exact bound
+ * gives; otherwise the exact bound is computed in the same step.  The nodes
+ * expanded, the incumbent and the result are those of the exact search;
+ * bound_evals and pixel_updates count exact bounds only. */
+#define ECMD_SEARCH_EXACT_BOUNDS 1u
+
 typedef struct {
     float d_lo, d_hi, eps;
-    float reserved0;
+    uint32_t flags;
     double gamma;
     int64_t max_nodes;
     int32_t frontier_batch;
@@ -117,7 +132,10 @@ typedef struct {
  * nu = -d_hat).  gap is 0 when the result is certified optimal; otherwise
  * an upper bound on (best contrast - returned contrast).  Counters:
  * event_hyp_evals = sum over evaluated hypotheses of the window's event
- * count; pixel_updates = upper-bound image increments. */
+ * count (exact bounds and points); pixel_updates = upper-bound image
+ * increments; bound_certs = child intervals kept on the endpoint certificate
+ * (see ecmd_search.flags), whose walks were not made.  A search cut short
+ * while such a node is queued reports gap = infinity. */
 typedef struct {
     int32_t status;
     uint32_t j_star;
@@ -137,6 +155,7 @@ typedef struct {
     int64_t pixel_updates;
     int32_t steps;
     int32_t seeded;
+    int64_t bound_certs;
 } ecmd_result;
 
 /* ------------------------------------------------------------ context */

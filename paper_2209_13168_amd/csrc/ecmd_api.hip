@@ -526,6 +526,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     sp.max_nodes = search->max_nodes;
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
+    sp.cert = (search->flags & ECMD_SEARCH_EXACT_BOUNDS) ? 0 : 1;
+    sp.pad = 0;
     const int T = g.T;
     set_groups(c, B, sp, T);
     HIPCHK(c, c->state.ensure(sizeof(WinState) * B));
@@ -548,8 +550,10 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     int nb = 0;
     HIPCHK(c, eval_setup(c, lds, nt, &nb));
     int active = B;
-    auto step_pair = [&](bool timed) -> hipError_t {
-        // two steps: parity 0 then 1, so the queue pair is back in place
+    auto run_step = [&](bool timed) -> hipError_t {
+        // one step: evaluate the step's hypotheses (queue set 0), frontier
+        // phase 0 (queues the exact bounds of failed certificates in set 1),
+        // evaluate those, frontier phase 1 (queues the next step in set 0)
         for (int parity = 0; parity < 2; ++parity) {
             hipEvent_t a = nullptr, b = nullptr;
             if (timed) tm.pair(0, a, b);
@@ -559,7 +563,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
                                        c->part.as<Part>(), sp.HS, nullptr, a, b);
             if (e != hipSuccess) return e;
             if (timed) tm.pair(1, a, b);
-            e = launch_frontier(c->stream, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
+            e = launch_frontier(c->stream, parity, sp, c->wp.as<WinParam>(), B, T, c->seg_off.as<long long>(),
                                 c->state.as<WinState>(), c->front.as<Node>(), c->sel.as<Sel>(), c->hyps.as<Hyp>(),
                                 c->act.as<int>(), c->part.as<Part>(), c->items.as<Item>(), qcap,
                                 &q[(1 - parity) * kXcd], c->n_active.as<int>(), a, b);
@@ -587,7 +591,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
             c->gexec = nullptr;
             hipGraph_t gr = nullptr;
             HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e1 = step_pair(false);
+            hipError_t e1 = run_step(false);
             hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
             HIPCHK(c, e1);
             HIPCHK(c, e2);
@@ -607,14 +611,14 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
     if (!pev[0] || !pev[1]) return fail(c, ECMD_EDEVICE, "hipEventCreate failed");
     auto enqueue_block = [&](int b) -> hipError_t {
         hipError_t e;
-        if (graph) {
-            if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return e;
-            if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return e;
-        } else {
-            if ((e = step_pair(true)) != hipSuccess) return e;
-            if ((e = step_pair(true)) != hipSuccess) return e;
-            tm.cut();
+        for (int k = 0; k < 4; ++k) {
+            if (graph) {
+                if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return e;
+            } else if ((e = run_step(true)) != hipSuccess) {
+                return e;
+            }
         }
+        if (!graph) tm.cut();
         char* slot = poll + 16 * (b & 1);
         if ((e = hipMemcpyAsync(slot, c->n_active.p, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
             return e;
@@ -672,7 +676,9 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         r.contrast = key_to_double(s.Kinc_hi, s.Kinc_lo) / M2;
         const double tau = (double)c->h_tau[w];
         r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * tau);
-        if (s.status == ECMD_EFRONTIER) r.gap = INFINITY;
+        // no finite gap certified: a frontier overflow, or a search cut
+        // short while a node kept on its endpoint certificate was queued
+        if (s.status == ECMD_EFRONTIER || s.gap_hi < 0) r.gap = INFINITY;
         else r.gap = key_to_double(s.gap_hi, s.gap_lo) / M2;
         r.n_events = c->h_off[w + 1] - c->h_off[w];
         r.nodes_expanded = s.nodes_expanded;
@@ -683,6 +689,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         r.pixel_updates = s.pixel_updates;
         r.steps = s.steps;
         r.seeded = s.seeded;
+        r.bound_certs = s.cert_evals;
         if (r.status != ECMD_OK && first_status == ECMD_OK) first_status = r.status;
     }
     return first_status;
@@ -863,6 +870,8 @@ static int plan_shape(ecmd_ctx* c, const ecmd_sensor* sensor, const ecmd_search*
     const long long M = (long long)W * H * npol;
     sp.gamma_key = search->gamma > 0.0 ? (long long)floor(search->gamma * (double)M * (double)M) : -1;
     sp.M = M;
+    sp.cert = (search->flags & ECMD_SEARCH_EXACT_BOUNDS) ? 0 : 1;
+    sp.pad = 0;
     sp.G = 1;
     sp.B = 1;
     sp.gslots = 0;
@@ -920,13 +929,13 @@ static int plan_enqueue(ecmd_ctx* c, const PlanShape& sh, void* const* b, const 
     HIPCHK(c, launch_init(s, sp, wp, d_seeds, B, st, sel, hyps, act, items, sh.qcap, &q[0], T, seg_off,
                           InitCheck{(const int*)b[PB_WSTAT], (const int*)b[PB_WERR], (long long)sh.lim.max_records}));
     for (int step = 0; step < sh.lim.max_steps; step += 4) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {  // four steps of two phases
             const int parity = k & 1;
             HIPCHK(c, launch_eval(s, g, sh.nb, sh.nt, sh.lds, (const float4*)b[PB_EV], seg_off,
                                   (const int*)b[PB_SEG_OWN], hyps, act, items, sh.qcap, &q[parity * kXcd],
                                   &q[(1 - parity) * kXcd], part, sp.HS, nullptr));
-            HIPCHK(c, launch_frontier(s, sp, wp, B, T, seg_off, st, (Node*)b[PB_FRONT], sel, hyps, act, part, items,
-                                      sh.qcap, &q[(1 - parity) * kXcd], (int*)b[PB_NACTIVE]));
+            HIPCHK(c, launch_frontier(s, parity, sp, wp, B, T, seg_off, st, (Node*)b[PB_FRONT], sel, hyps, act, part,
+                                      items, sh.qcap, &q[(1 - parity) * kXcd], (int*)b[PB_NACTIVE]));
         }
         // bin again with the live ranges, at the synchronous call's polling
         // points (unconditionally: the host does not see the copy count)

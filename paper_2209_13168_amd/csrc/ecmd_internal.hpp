@@ -29,7 +29,10 @@ constexpr int kEvalThreads = 1024;  // threads of the largest evaluation workgro
 constexpr int kEvalPad = 2 * kEvalThreads;  // records after the event store: the evaluation kernel prefetches up to two workgroup strides past a segment's end
 constexpr int kFrontThreads = 256;  // threads of a frontier workgroup
 
-enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2 };
+// HYP_CERT: the endpoint certificate of an interval (owned events only, no
+// walk): partial sums S = U (walk pixels of the events inside at both ends),
+// N = N_low; K_bar >= U^2 - N_low^2.
+enum HypKind : int { HYP_NONE = 0, HYP_POINT = 1, HYP_INTERVAL = 2, HYP_CERT = 3 };
 
 struct Hyp {
     float ra, rb;  // rates of the interval ends (equal for a point)
@@ -47,11 +50,21 @@ struct Part {
 struct Node {
     unsigned long long klo;  // key K_bar, low and high 64-bit words
     long long khi;
-    unsigned ja, jb;  // grid interval [ja, jb]
+    unsigned ja, jb;  // grid interval [ja, jb]; jb carries kNodeCert
+    float lc;         // expected endpoint certificate of this node's children
+    unsigned pad;
 };
+
+// Set in Node::jb when the key is the endpoint certificate (a lower bound of
+// K_bar) rather than K_bar itself (grid indices stay below 2^31).
+constexpr unsigned kNodeCert = 0x80000000u;
+// Node::khi of a child whose certificate failed, queued in its place until
+// its exact bound (hypothesis slot Node::klo) is known later in the step.
+constexpr long long kNodeRepair = (long long)(-0x7fffffffffffffffll - 1);
 
 struct Sel {
     unsigned ja, jb, jc, kids;  // expanded node, its centre, 1 if it has children
+    float lc;                   // expected endpoint certificate of its children (Node::lc)
 };
 
 struct Geometry {
@@ -85,6 +98,8 @@ struct Search {
     long long max_nodes;
     long long gamma_key;  // stop when best K_bar - K_inc <= gamma_key (-1: gamma = 0)
     long long M;          // pixels
+    int cert;             // endpoint certificates allowed (ECMD_SEARCH_EXACT_BOUNDS not set)
+    int pad;
 };
 
 struct WinState {
@@ -102,6 +117,11 @@ struct WinState {
     int pad;
     long long nodes_expanded, nodes_pruned, point_evals, bound_evals;
     long long event_hyp, pixel_updates;
+    long long cert_evals;  // certificates that kept their node
+    int n_repair;          // children whose certificate failed, bounded again this step
+    int overflow;          // the frontier outgrew its capacity this step
+    int n_front0;          // queued nodes before this step's children
+    int pad2;
 };
 
 // A work item: tile t of window w for the hypotheses act[w * HS + r0 + k],
@@ -157,8 +177,13 @@ struct InitCheck {
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
                        WinState* st, Sel* sel, Hyp* hyps, int* act, Item* items, int qcap, Queue* q, int T,
                        const long long* seg_off, InitCheck chk);
+// One step of Algorithm 1 in two launches around an evaluation launch:
+// phase 0 absorbs the step's evaluations (incumbent, children) and queues
+// the exact bound of every child whose endpoint certificate failed (in
+// q_fill, usually nothing); phase 1 absorbs those bounds, prunes, stops or
+// selects the next nodes and queues their hypotheses in q_fill.
 // t0, t1 (nullable): events that take the kernel's own start and end times
-hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
+hipError_t launch_frontier(hipStream_t s, int phase, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active,
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);

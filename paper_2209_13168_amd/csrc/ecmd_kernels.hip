@@ -55,6 +55,25 @@ __device__ __forceinline__ void sp128(i128 v, long long& hi, unsigned long long&
     hi = (long long)(unsigned long long)(u >> 64);
 }
 
+// Correctly rounded conversion of a 128-bit integer to double: the top 64
+// significant bits, with a sticky bit for any below them, are converted
+// (one rounding) and scaled by a power of two (exact).
+__device__ __forceinline__ double i128_to_double(i128 v) {
+    const bool neg = v < 0;
+    const unsigned __int128 u = neg ? (unsigned __int128)0 - (unsigned __int128)v : (unsigned __int128)v;
+    const unsigned long long hi = (unsigned long long)(u >> 64);
+    double r;
+    if (hi == 0) {
+        r = (double)(unsigned long long)u;
+    } else {
+        const int sh = 64 - __clzll(hi);
+        unsigned long long top = (unsigned long long)(u >> sh);
+        top |= (u & ((((unsigned __int128)1) << sh) - 1)) != 0 ? 1ull : 0ull;
+        r = ldexp((double)top, sh);
+    }
+    return neg ? -r : r;
+}
+
 __device__ __forceinline__ bool improvable(i128 key, unsigned ja, i128 Kinc, unsigned jinc) {
     return key > Kinc || (key == Kinc && (unsigned long long)ja + 1ull < (unsigned long long)jinc);
 }
@@ -558,7 +577,36 @@ __global__ __launch_bounds__(NT) void k_eval(
         const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
         const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
         visits = (unsigned)tid < nseg ? (nseg - 1u - (unsigned)tid) / NT + 1u : 0u;
-        if (hp.kind == HYP_POINT) {
+        unsigned long long ucert = 0;  // certificate: walk pixels of the events inside at both ends
+        if (hp.kind == HYP_CERT) {
+            // Endpoint certificate of an interval (eqs. (17)-(20) without
+            // the walk): the owned events only, no counter is touched.  An
+            // event with both endpoint pixels in the image walks through
+            // |dkx| + |dky| + 1 distinct image pixels at least.
+            const float ra = hp.ra, rb = hp.rb;
+            visits = 0;
+            unsigned nl = 0;
+            const auto one = [&](const float4& e) {
+                const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
+                const int kxb = flr_clamp(fmaf(e.z, rb, e.x), g.W), kyb = flr_clamp(fmaf(e.w, rb, e.y), g.H);
+                const bool full = (umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
+                                  (umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
+                nl += full ? 1u : 0u;
+                ucert += full ? (unsigned)(abs(kxb - kxa) + abs(kyb - kya) + 1) : 0u;
+            };
+            constexpr int U = 4;
+            constexpr unsigned S = NT;
+            unsigned i = tid;
+            for (; i + (U - 1) * S < nown; i += U * S) {
+                float4 e[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) e[k] = at(i + k * S);
+#pragma unroll
+                for (int k = 0; k < U; ++k) one(e[k]);
+            }
+            for (; i < nown; i += S) one(at(i));
+            nlow = nl;
+        } else if (hp.kind == HYP_POINT) {
             // Point hypothesis (eqs. (12)-(13)): U events per thread in
             // flight, loads first, then U increments without branches.
             const float r = hp.ra;
@@ -630,27 +678,30 @@ __global__ __launch_bounds__(NT) void k_eval(
         // read, and the region is zeroed for the next hypothesis (every
         // counter is zero between hypotheses).  Each thread takes some
         // counters (its own sums may wrap; the workgroup's totals are exact).
+        // (A certificate touched no counter: it skips both passes, not the
+        // barrier, which also orders thread 0's reads of the reduction
+        // scratch before the next writes.)
         __syncthreads();
-        unsigned long long sq = 0, hits = visits;
-        for (int k = tid; k < nring; k += NT) {
-            int idx;
-            if (k < R.rw) idx = k;                                      // top row
-            else if (k < 2 * R.rw) idx = (th + 1) * R.rw + (k - R.rw);  // bottom row
-            else idx = (1 + ((k - 2 * R.rw) >> 1)) * R.rw + (((k - 2 * R.rw) & 1) ? R.rw - 1 : 0);
-            const unsigned m = tile[idx];
-            sq -= (unsigned long long)m * m;
-            hits -= m;
-        }
-        if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
-            const long long M = (long long)g.W * g.H;
-            unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
-            for (int k = tid; k < tw * th; k += NT) {
-                const int lx = k % tw, ly = k / tw;
-                im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
+        unsigned long long sq = ucert, hits = visits;
+        if (hp.kind != HYP_CERT) {
+            for (int k = tid; k < nring; k += NT) {
+                int idx;
+                if (k < R.rw) idx = k;                                      // top row
+                else if (k < 2 * R.rw) idx = (th + 1) * R.rw + (k - R.rw);  // bottom row
+                else idx = (1 + ((k - 2 * R.rw) >> 1)) * R.rw + (((k - 2 * R.rw) & 1) ? R.rw - 1 : 0);
+                const unsigned m = tile[idx];
+                sq -= (unsigned long long)m * m;
+                hits -= m;
             }
-        }
-        __syncthreads();  // every read of single counters is done before the region is zeroed
-        {
+            if (img_out) {  // hypothesis wh's image(s): W*H cells per polarity image
+                const long long M = (long long)g.W * g.H;
+                unsigned* const im = img_out + (long long)wh * M * (g.T / g.nsp) + (long long)(t / g.nsp) * M;
+                for (int k = tid; k < tw * th; k += NT) {
+                    const int lx = k % tw, ly = k / tw;
+                    im[(long long)(y0 + ly) * g.W + (x0 + lx)] = tile[(ly + 1) * R.rw + lx + 1];
+                }
+            }
+            __syncthreads();  // every read of single counters is done before the region is zeroed
             uint4* const t4 = reinterpret_cast<uint4*>(tile);
             const int n4 = (ncnt + 3) >> 2;  // the counters lie in the rounded-up region
             for (int i = tid; i < n4; i += NT) {
@@ -820,44 +871,15 @@ __device__ __forceinline__ void slot_sums(const Part* pw, int slot, int T, const
     }
 }
 
-// Hypotheses of the selected nodes, the list of active slots, and the work
-// items: groups of up to G active slots on each non-empty tile, tile-major.
-__device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
-                          const Sel* sl, int n_sel, Hyp* hy, int* act, Item* items, int qcap, Queue* qf,
-                          int* s_wave) {
-    const int F = sp.F, HS = sp.HS;
+// Work items of the na active slots act[0..na) of window w: groups of up
+// to G slots on each non-empty tile, tile-major, appended to the window's
+// queue in qf.
+__device__ void emit_items(const Search& sp, int w, const int* tiles, int nt, int na, Item* items, int qcap,
+                           Queue* qf) {
     int G = sp.G;
     const int qr = w % kXcd;  // this window's queue
     Item* qitems = items + (long long)qr * qcap;
     __shared__ int s_base;
-    int na = 0;  // active slots so far
-    for (int h0 = 0; h0 < HS; h0 += NTF) {
-        const int h = h0 + threadIdx.x;
-        Hyp hp;
-        hp.kind = HYP_NONE;
-        hp.pad = 0;
-        hp.ra = hp.rb = 0.0f;
-        if (h < F) {
-            if (h < n_sel) {
-                hp.kind = HYP_POINT;
-                hp.ra = hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, sl[h].jc), p.tau);
-            }
-        } else if (h < HS) {
-            const int c = h - F, i = c >> 1;
-            if (i < n_sel && sl[i].kids) {
-                const unsigned a = (c & 1) ? sl[i].jc : sl[i].ja;
-                const unsigned b = (c & 1) ? sl[i].jb : sl[i].jc;
-                hp.kind = HYP_INTERVAL;
-                hp.ra = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, a), p.tau);
-                hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, b), p.tau);
-            }
-        }
-        if (h < HS) hy[h] = hp;
-        int tot;
-        const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
-        if (hp.kind != HYP_NONE) act[na + r] = h;
-        na += tot;
-    }
     if (sp.gslots > 0) {  // this step's items with one hypothesis each, all windows alike
         const long long work = (long long)sp.B * na * nt;
         G = (int)max(1ll, min((long long)G, work / sp.gslots));
@@ -876,6 +898,52 @@ __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, con
         qitems[s_base + ti * ng + (ng - 1 - gi)] = it;
     }
     __syncthreads();
+}
+
+// Hypotheses of the selected nodes, the list of active slots, and the work
+// items.  q_rem: nodes left in the queue; n_kids: selected nodes with
+// children.  When every node the queue can hold after the next step is
+// expanded at that step (q_rem + 2 n_kids <= F), gamma is 0 and there is no
+// node budget, a child's bound value decides nothing but whether it is
+// kept, so the children get the endpoint certificate (exact bounds when it
+// fails, in the same step).
+__device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
+                          const Sel* sl, int n_sel, int q_rem, int n_kids, float kinc, Hyp* hy, int* act,
+                          Item* items, int qcap, Queue* qf, int* s_wave) {
+    const int F = sp.F, HS = sp.HS;
+    const bool cert = sp.cert && sp.gamma_key < 0 && sp.max_nodes == 0 && q_rem + 2 * n_kids <= F &&
+                      q_rem + 2 * n_kids <= sp.CAP;
+    // a node's children take the certificate when it is expected to clear
+    // the incumbent K_inc (kinc) with a margin
+    int na = 0;  // active slots so far
+    for (int h0 = 0; h0 < HS; h0 += NTF) {
+        const int h = h0 + threadIdx.x;
+        Hyp hp;
+        hp.kind = HYP_NONE;
+        hp.pad = 0;
+        hp.ra = hp.rb = 0.0f;
+        if (h < F) {
+            if (h < n_sel) {
+                hp.kind = HYP_POINT;
+                hp.ra = hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, sl[h].jc), p.tau);
+            }
+        } else if (h < HS) {
+            const int c = h - F, i = c >> 1;
+            if (i < n_sel && sl[i].kids) {
+                const unsigned a = (c & 1) ? sl[i].jc : sl[i].ja;
+                const unsigned b = (c & 1) ? sl[i].jb : sl[i].jc;
+                hp.kind = (cert && sl[i].lc > 1.5f * kinc) ? HYP_CERT : HYP_INTERVAL;
+                hp.ra = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, a), p.tau);
+                hp.rb = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, b), p.tau);
+            }
+        }
+        if (h < HS) hy[h] = hp;
+        int tot;
+        const int r = block_scan(hp.kind != HYP_NONE ? 1 : 0, s_wave, tot);
+        if (hp.kind != HYP_NONE) act[na + r] = h;
+        na += tot;
+    }
+    emit_items(sp, w, tiles, nt, na, items, qcap, qf);
 }
 
 __device__ __forceinline__ void nonempty_tiles(int w, int T, const long long* seg_off, int* tiles, int* s_nt,
@@ -927,6 +995,7 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
         root.jb = top;
         root.jc = top >> 1;
         root.kids = (top >= 4) ? 1u : 0u;
+        root.lc = INFINITY;  // no evaluation yet: the root's children try the certificate
         sl[0] = root;
         int n_sel = 1;
         if (seeds) {
@@ -940,6 +1009,7 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
                     Sel sd;
                     sd.ja = sd.jb = sd.jc = (unsigned)j;
                     sd.kids = 0;
+                    sd.lc = 0.0f;
                     sl[1] = sd;
                     n_sel = 2;
                 }
@@ -953,8 +1023,8 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
     }
     __syncthreads();
     nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
-    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, hyps + (long long)w * sp.HS, act + (long long)w * sp.HS,
-              items, qcap, q, s_wave);
+    emit_hyps(sp, wp[w], w, T, s_tiles, s_nt, sl, s_nsel, 0, 1, -1.0f, hyps + (long long)w * sp.HS,
+              act + (long long)w * sp.HS, items, qcap, q, s_wave);
 }
 
 hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, const float* seeds, int B,
@@ -965,12 +1035,37 @@ hipError_t launch_init(hipStream_t s, const Search& sp, const WinParam* wp, cons
     return hipGetLastError();
 }
 
-// One step of Algorithm 1 for window blockIdx.x: absorb the evaluated
-// hypotheses, update the incumbent, queue the improvable children, drop
-// queued nodes that can no longer improve, decide whether to stop, select
-// the next nodes, emit their hypotheses.  Every order below is the array
+// The certificate a node's children can expect, from the node's own sums:
+// U walk pixels over N_low events inside at both ends, i.e. mean walk
+// length l = U / N_low - 1; a child's walks are about half as long, so its
+// certificate is about N_low^2 (l/2)(l/2 + 2).  Only the choice between the
+// certificate and the exact bound depends on it, never a result.
+__device__ __forceinline__ float child_cert(unsigned long long U, long long N) {
+    if (N <= 0) return 0.0f;
+    const float l = fmaxf((float)U / (float)N - 1.0f, 0.0f) * 0.5f;
+    return (float)N * (float)N * l * (l + 2.0f);
+}
+
+// Append the children whose keep flag is set to the queue (array order),
+// noting an overflow of the capacity.
+__device__ __forceinline__ void queue_append(Node* fr, int& n, int CAP, bool keep, const Node& nd, int* s_wave,
+                                             int& overflow) {
+    int tot;
+    const int r = block_scan(keep ? 1 : 0, s_wave, tot);
+    if (keep && n + r < CAP) fr[n + r] = nd;
+    if (n + tot > CAP) overflow = 1;
+    n = min(n + tot, CAP);
+}
+
+// Phase 0 of one step of Algorithm 1 for window blockIdx.x: absorb the
+// evaluated hypotheses, update the incumbent and queue the improvable
+// children.  A child evaluated by its endpoint certificate L <= K_bar is
+// queued with key L (marked kNodeCert) when L already shows it improvable;
+// otherwise it is queued in its place as a placeholder (kNodeRepair) and its
+// exact bound goes to the evaluation launch between the phases, so the
+// queue keeps the exact search's order.  Every order below is the array
 // order (scans, no atomic slot races), so the search is reproducible.
-__global__ __launch_bounds__(NTF) void k_frontier(
+__global__ __launch_bounds__(NTF) void k_frontier_a(
     Search sp, const WinParam* __restrict__ wp, int B, int T, const long long* __restrict__ seg_off,
     WinState* __restrict__ st, Node* __restrict__ front, Sel* __restrict__ sel, Hyp* __restrict__ hyps,
     int* __restrict__ act, const Part* __restrict__ part, Item* __restrict__ items, int qcap,
@@ -981,10 +1076,8 @@ __global__ __launch_bounds__(NTF) void k_frontier(
     __shared__ unsigned long long s_lo[NTF];
     __shared__ unsigned s_j[NTF];
     __shared__ int s_wave[NWF], s_tiles[kMaxTiles], s_nt;
-    __shared__ int s_hist[130];
-    __shared__ int s_bstar, s_quota, s_stop, s_take;
     __shared__ unsigned long long s_pix;
-    __shared__ long long s_nbound, s_pruned;
+    __shared__ long long s_nbound, s_pruned, s_ncert;
     if (tid == 0) s = st[w];
     __syncthreads();
     if (!s.active) return;
@@ -993,6 +1086,8 @@ __global__ __launch_bounds__(NTF) void k_frontier(
     const WinParam p = wp[w];
     Node* fr = front + (long long)w * CAP;
     Sel* sl = sel + (long long)w * F;
+    Hyp* hy = hyps + (long long)w * HS;
+    int* ac = act + (long long)w * HS;
     const Part* pw = part + (long long)w * HS * T;
     nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
     const int nt = s_nt;
@@ -1020,44 +1115,145 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s_pix = 0;
         s_nbound = 0;
         s_pruned = 0;
+        s_ncert = 0;
     }
-    for (int b = tid; b < 130; b += NTF) s_hist[b] = 0;
     __syncthreads();
 
     // (2) children of the expanded nodes, appended in slot order
     int n = s.n_front;
-    int overflow = 0;
+    const int n0 = n;
+    int overflow = 0, nrep = 0;
     for (int c0 = 0; c0 < 2 * n_sel; c0 += NTF) {
         const int c = c0 + tid;
-        int keep = 0;
+        bool keep = false, rep = false;
         Node nd;
         if (c < 2 * n_sel && sl[c >> 1].kids) {
             unsigned long long S, U;
             long long N;
             slot_sums(pw, F + c, T, s_tiles, nt, S, N, U);
-            atomicAdd(&s_pix, U);
-            atomicAdd((unsigned long long*)&s_nbound, 1ull);
-            const i128 Kb = (i128)M * (i128)S - (i128)N * (i128)N;
             const Sel x = sl[c >> 1];
             nd.ja = (c & 1) ? x.jc : x.ja;
             nd.jb = (c & 1) ? x.jb : x.jc;
-            sp128(Kb, nd.khi, nd.klo);
-            keep = improvable(Kb, nd.ja, Kinc, jinc) ? 1 : 0;
-            if (!keep) atomicAdd((unsigned long long*)&s_pruned, 1ull);
+            nd.pad = 0;
+            if (hy[F + c].kind == HYP_CERT) {
+                // S holds U (walk pixels of the events inside at both ends):
+                // M S_bar >= U^2 (Cauchy-Schwarz over the M cells)
+                const i128 Lb = (i128)S * (i128)S - (i128)N * (i128)N;
+                nd.lc = child_cert(S, N);
+                keep = true;
+                if (improvable(Lb, nd.ja, Kinc, jinc)) {
+                    sp128(Lb, nd.khi, nd.klo);
+                    nd.jb |= kNodeCert;
+                    atomicAdd((unsigned long long*)&s_ncert, 1ull);
+                } else {
+                    rep = true;
+                    nd.khi = kNodeRepair;
+                    nd.klo = (unsigned long long)(F + c);
+                }
+            } else {
+                atomicAdd(&s_pix, U);
+                atomicAdd((unsigned long long*)&s_nbound, 1ull);
+                const i128 Kb = (i128)M * (i128)S - (i128)N * (i128)N;
+                sp128(Kb, nd.khi, nd.klo);
+                nd.lc = child_cert(U, N);
+                keep = improvable(Kb, nd.ja, Kinc, jinc);
+                if (!keep) atomicAdd((unsigned long long*)&s_pruned, 1ull);
+            }
         }
+        queue_append(fr, n, CAP, keep, nd, s_wave, overflow);
+        // the children to bound exactly between the phases
         int tot;
-        const int r = block_scan(keep, s_wave, tot);
-        if (keep) {
-            if (n + r < CAP) fr[n + r] = nd;
+        const int r = block_scan(rep ? 1 : 0, s_wave, tot);
+        if (rep) {
+            hy[F + c].kind = HYP_INTERVAL;  // same end rates
+            ac[nrep + r] = F + c;
         }
-        if (n + tot > CAP) overflow = 1;
-        n = min(n + tot, CAP);
+        nrep += tot;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s.bound_evals += s_nbound;
+        s.event_hyp += s_nbound * p.n_events;
+        s.pixel_updates += (long long)s_pix;
+        s.nodes_pruned += s_pruned;
+        s.cert_evals += s_ncert;
+        s.n_front = n;
+        s.n_front0 = n0;
+        s.overflow = overflow;
+        s.n_repair = nrep;
+        st[w] = s;
+    }
+    if (nrep) emit_items(sp, w, s_tiles, nt, nrep, items, qcap, qf);
+}
+
+// Phase 1 of the step: put the exact bounds of the children whose
+// certificate failed into their placeholders, drop queued nodes that can no
+// longer improve, decide whether to stop, select the next nodes, emit their
+// hypotheses.
+__global__ __launch_bounds__(NTF) void k_frontier_b(
+    Search sp, const WinParam* __restrict__ wp, int B, int T, const long long* __restrict__ seg_off,
+    WinState* __restrict__ st, Node* __restrict__ front, Sel* __restrict__ sel, Hyp* __restrict__ hyps,
+    int* __restrict__ act, const Part* __restrict__ part, Item* __restrict__ items, int qcap,
+    Queue* __restrict__ qf, int* __restrict__ n_active) {
+    const int w = blockIdx.x, tid = threadIdx.x;
+    __shared__ WinState s;
+    __shared__ long long s_hi[NTF];
+    __shared__ unsigned long long s_lo[NTF];
+    __shared__ unsigned s_j[NTF];
+    __shared__ int s_wave[NWF], s_tiles[kMaxTiles], s_nt;
+    __shared__ int s_hist[130];
+    __shared__ int s_bstar, s_quota, s_stop, s_take, s_anycert;
+    __shared__ unsigned long long s_pix;
+    __shared__ long long s_nbound, s_pruned;
+    if (tid == 0) s = st[w];
+    __syncthreads();
+    if (!s.active) return;
+    const int F = sp.F, HS = sp.HS, CAP = sp.CAP;
+    const long long M = sp.M;
+    const WinParam p = wp[w];
+    Node* fr = front + (long long)w * CAP;
+    Sel* sl = sel + (long long)w * F;
+    const Part* pw = part + (long long)w * HS * T;
+    nonempty_tiles(w, T, seg_off, s_tiles, &s_nt, s_wave);
+    const int nt = s_nt;
+    const i128 Kinc = mk128(s.Kinc_hi, s.Kinc_lo);
+    const unsigned jinc = s.j_inc;
+    if (tid == 0) {
+        s_pix = 0;
+        s_nbound = 0;
+        s_pruned = 0;
+        s_anycert = 0;
+    }
+    for (int b = tid; b < 130; b += NTF) s_hist[b] = 0;
+    __syncthreads();
+
+    // (2') the exact bounds of the children whose certificate failed, into
+    // their placeholders (this step's children sit at [n_front0, n_front));
+    // one that cannot improve is dropped below with the other such nodes
+    const int n = s.n_front;
+    const int overflow = s.overflow;
+    if (s.n_repair) {
+        for (int i = s.n_front0 + tid; i < n; i += NTF) {
+            Node nd = fr[i];
+            if (nd.khi != kNodeRepair) continue;
+            unsigned long long S, U;
+            long long N;
+            slot_sums(pw, (int)nd.klo, T, s_tiles, nt, S, N, U);
+            atomicAdd(&s_pix, U);
+            atomicAdd((unsigned long long*)&s_nbound, 1ull);
+            const i128 Kb = (i128)M * (i128)S - (i128)N * (i128)N;
+            sp128(Kb, nd.khi, nd.klo);
+            if (!improvable(Kb, nd.ja, Kinc, jinc)) atomicAdd((unsigned long long*)&s_pruned, 1ull);
+            fr[i] = nd;
+        }
     }
     __syncthreads();
 
     // (3) which queued nodes can still improve; histogram of their gap
     // sizes; the node Algorithm 1 would pop next (largest bound, ties to the
-    // smaller grid index; queued intervals are disjoint, so ja names it)
+    // smaller grid index; queued intervals are disjoint, so ja names it).
+    // A certificate key is only a lower bound of K_bar, so while such a node
+    // is queued no finite gap is certified.
     i128 best_gap = -1;
     unsigned best_ja = 0xFFFFFFFFu;
     for (int i = tid; i < n; i += NTF) {
@@ -1066,6 +1262,7 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         if (improvable(k, nd.ja, Kinc, jinc)) {
             const i128 gap = k - Kinc;
             atomicAdd(&s_hist[bitlen128(gap)], 1);
+            if (nd.jb & kNodeCert) s_anycert = 1;
             if (gap > best_gap || (gap == best_gap && nd.ja < best_ja)) {
                 best_gap = gap;
                 best_ja = nd.ja;
@@ -1084,8 +1281,8 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s.pixel_updates += (long long)s_pix;
         s.nodes_pruned += s_pruned;
         // the gap certified so far (queued and selected nodes), kept for a
-        // search that is cut short after this step
-        sp128(best_gap < 0 ? (i128)0 : best_gap, s.gap_hi, s.gap_lo);
+        // search that is cut short after this step (-1: none certified)
+        sp128(s_anycert ? (i128)-1 : best_gap < 0 ? (i128)0 : best_gap, s.gap_hi, s.gap_lo);
         int stop = 0;
         if (overflow) {
             s.status = -5;  // ECMD_EFRONTIER
@@ -1140,10 +1337,10 @@ __global__ __launch_bounds__(NTF) void k_frontier(
     // More: every node of the larger gap classes and the first `quota`
     // of class b* in queue order.
     const bool pop_one = s_take == 1;
-    int out = 0, nsel = 0, inb = 0;
+    int out = 0, nsel = 0, inb = 0, nkids = 0;
     for (int base = 0; base < n; base += NTF) {
         const int i = base + tid;
-        Node nd;
+        Node nd = Node{};
         int keep = 0, cand = 0, big = 0;
         if (i < n) {
             nd = fr[i];
@@ -1165,20 +1362,25 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         const int take = big || (cand && inb + rc < s_quota);
         if (cand && !take) keep = 1;
         inb += tot_c;
-        int tot_k, tot_t;
+        const unsigned jb = nd.jb & ~kNodeCert;
+        const int kids = take && jb - nd.ja >= 4;
+        int tot_k, tot_t, tot_d;
         const int rk = block_scan(keep, s_wave, tot_k);
         const int rt = block_scan(take, s_wave, tot_t);
+        block_scan(kids, s_wave, tot_d);
         if (keep) fr[out + rk] = nd;
         if (take) {
             Sel x;
             x.ja = nd.ja;
-            x.jb = nd.jb;
-            x.jc = (nd.ja + nd.jb) >> 1;
-            x.kids = (nd.jb - nd.ja >= 4) ? 1u : 0u;
+            x.jb = jb;
+            x.jc = (nd.ja + jb) >> 1;
+            x.kids = kids ? 1u : 0u;
+            x.lc = nd.lc;
             sl[nsel + rt] = x;
         }
         out += tot_k;
         nsel += tot_t;
+        nkids += tot_d;
     }
     __syncthreads();
     if (tid == 0) {
@@ -1188,8 +1390,8 @@ __global__ __launch_bounds__(NTF) void k_frontier(
         s.steps += 1;
         st[w] = s;
     }
-    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, hyps + (long long)w * HS, act + (long long)w * HS, items, qcap, qf,
-              s_wave);
+    emit_hyps(sp, p, w, T, s_tiles, nt, sl, nsel, out, nkids, (float)i128_to_double(Kinc), hyps + (long long)w * HS,
+              act + (long long)w * HS, items, qcap, qf, s_wave);
 }
 
 // Grid range still alive in each active window: the queued nodes and those
@@ -1215,7 +1417,7 @@ __global__ __launch_bounds__(NTF) void k_live_range(Search sp, const WinState* _
     unsigned lo = 0xFFFFFFFFu, hi = 0u;
     for (int i = tid; i < s.n_front; i += NTF) {
         lo = min(lo, fr[i].ja);
-        hi = max(hi, fr[i].jb);
+        hi = max(hi, fr[i].jb & ~kNodeCert);
     }
     for (int i = tid; i < s.n_sel; i += NTF) {
         lo = min(lo, sl[i].ja);
@@ -1239,13 +1441,17 @@ hipError_t launch_live_range(hipStream_t s, const Search& sp, const WinState* st
     return hipGetLastError();
 }
 
-hipError_t launch_frontier(hipStream_t s, const Search& sp, const WinParam* wp, int B, int T,
+hipError_t launch_frontier(hipStream_t s, int phase, const Search& sp, const WinParam* wp, int B, int T,
                            const long long* seg_off, WinState* st, Node* front, Sel* sel, Hyp* hyps, int* act,
                            const Part* part, Item* items, int qcap, Queue* q_fill, int* n_active, hipEvent_t t0,
                            hipEvent_t t1) {
     if (B <= 0) return hipSuccess;
-    hipExtLaunchKernelGGL(k_frontier, dim3(B), dim3(NTF), 0u, s, t0, t1, 0u, sp, wp, B, T, seg_off, st, front, sel,
-                          hyps, act, part, items, qcap, q_fill, n_active);
+    if (phase == 0)
+        hipExtLaunchKernelGGL(k_frontier_a, dim3(B), dim3(NTF), 0u, s, t0, t1, 0u, sp, wp, B, T, seg_off, st, front,
+                              sel, hyps, act, part, items, qcap, q_fill, n_active);
+    else
+        hipExtLaunchKernelGGL(k_frontier_b, dim3(B), dim3(NTF), 0u, s, t0, t1, 0u, sp, wp, B, T, seg_off, st, front,
+                              sel, hyps, act, part, items, qcap, q_fill, n_active);
     return hipGetLastError();
 }
 
@@ -1329,25 +1535,6 @@ __global__ void k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
-// Correctly rounded conversion of a 128-bit integer to double: the top 64
-// significant bits, with a sticky bit for any below them, are converted
-// (one rounding) and scaled by a power of two (exact).
-__device__ __forceinline__ double i128_to_double(i128 v) {
-    const bool neg = v < 0;
-    const unsigned __int128 u = neg ? (unsigned __int128)0 - (unsigned __int128)v : (unsigned __int128)v;
-    const unsigned long long hi = (unsigned long long)(u >> 64);
-    double r;
-    if (hi == 0) {
-        r = (double)(unsigned long long)u;
-    } else {
-        const int sh = 64 - __clzll(hi);
-        unsigned long long top = (unsigned long long)(u >> sh);
-        top |= (u & ((((unsigned __int128)1) << sh) - 1)) != 0 ? 1ull : 0ull;
-        r = ldexp((double)top, sh);
-    }
-    return neg ? -r : r;
-}
-
 // Per-window results of a plan launch, written to `out` (device memory or
 // pinned host memory), with the same arithmetic as a synchronous call.
 __global__ void k_plan_results(Search sp, int B, const WinState* __restrict__ st, const long long* __restrict__ off,
@@ -1371,7 +1558,9 @@ __global__ void k_plan_results(Search sp, int B, const WinState* __restrict__ st
     r.contrast = i128_to_double(mk128(s.Kinc_hi, s.Kinc_lo)) / M2;
     const double t = (double)tau[w];
     r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * t);
-    r.gap = s.status == -5 ? (double)INFINITY : i128_to_double(mk128(s.gap_hi, s.gap_lo)) / M2;
+    // no finite gap certified: a frontier overflow, or a search cut short
+    // while a node kept on its endpoint certificate was queued
+    r.gap = (s.status == -5 || s.gap_hi < 0) ? (double)INFINITY : i128_to_double(mk128(s.gap_hi, s.gap_lo)) / M2;
     r.n_events = off[w + 1] - off[w];
     r.nodes_expanded = s.nodes_expanded;
     r.nodes_pruned = s.nodes_pruned;
@@ -1381,6 +1570,7 @@ __global__ void k_plan_results(Search sp, int B, const WinState* __restrict__ st
     r.pixel_updates = s.pixel_updates;
     r.steps = s.steps;
     r.seeded = s.seeded;
+    r.bound_certs = s.cert_evals;
     out[w] = r;
 }
 

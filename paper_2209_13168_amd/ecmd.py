@@ -20,6 +20,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_build", "libecmd.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EBUDGET, EFRONTIER = 0, -1, -2, -3, -4, -5
+SEARCH_EXACT_BOUNDS = 1  # ecmd_search.flags: every child interval gets the exact bound
 DEVICE_PTR = 1
 CNN_NPARAM = 23361
 GRID = 64
@@ -44,7 +45,7 @@ class WindowS(C.Structure):
 
 
 class SearchS(C.Structure):
-    _fields_ = [("d_lo", C.c_float), ("d_hi", C.c_float), ("eps", C.c_float), ("reserved0", C.c_float),
+    _fields_ = [("d_lo", C.c_float), ("d_hi", C.c_float), ("eps", C.c_float), ("flags", C.c_uint32),
                 ("gamma", C.c_double), ("max_nodes", C.c_int64), ("frontier_batch", C.c_int32),
                 ("frontier_capacity", C.c_int32)]
 
@@ -55,7 +56,7 @@ class ResultS(C.Structure):
                 ("K_lo", C.c_uint64), ("K_hi", C.c_int64), ("n_events", C.c_int64),
                 ("nodes_expanded", C.c_int64), ("nodes_pruned", C.c_int64), ("point_evals", C.c_int64),
                 ("bound_evals", C.c_int64), ("event_hyp_evals", C.c_int64), ("pixel_updates", C.c_int64),
-                ("steps", C.c_int32), ("seeded", C.c_int32)]
+                ("steps", C.c_int32), ("seeded", C.c_int32), ("bound_certs", C.c_int64)]
 
 
 class PlanInfo(C.Structure):
@@ -98,6 +99,7 @@ class Result:
     pixel_updates: int
     steps: int
     seeded: int
+    bound_certs: int
 
     @classmethod
     def of(cls, r: ResultS) -> "Result":
@@ -220,9 +222,10 @@ class _Args:
         return DEVICE_PTR if self.device else 0
 
 
-def _search(d_lo, d_hi, eps, gamma=0.0, max_nodes=0, frontier_batch=0, frontier_capacity=0) -> SearchS:
-    return SearchS(float(d_lo), float(d_hi), float(eps), 0.0, float(gamma), int(max_nodes),
-                   int(frontier_batch), int(frontier_capacity))
+def _search(d_lo, d_hi, eps, gamma=0.0, max_nodes=0, frontier_batch=0, frontier_capacity=0,
+            exact_bounds=False) -> SearchS:
+    return SearchS(float(d_lo), float(d_hi), float(eps), SEARCH_EXACT_BOUNDS if exact_bounds else 0, float(gamma),
+                   int(max_nodes), int(frontier_batch), int(frontier_capacity))
 
 
 def plan(sensor: Sensor, d_lo: float, d_hi: float, eps: float, polarity: bool = False, lds_bytes: int = 0,
@@ -354,14 +357,14 @@ class Context:
     # ---------------------------------------------------------- estimation
     def estimate(self, sensor: Sensor, x, y, t, t0: float, t1: float, d_lo: float, d_hi: float, eps: float,
                  gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0, frontier_capacity: int = 0,
-                 d_seed: Optional[float] = None, polarity=None) -> Result:
+                 d_seed: Optional[float] = None, polarity=None, exact_bounds: bool = False) -> Result:
         """One window [t0, t1] of a stream; polarity (int8, optional) selects
         the polarity-aware contrast."""
         a = _Args()
         n = int(x.shape[0])
         ev = EventsS(a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t, np.float64), n,
                      a.ptr(polarity, np.int8))
-        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity, exact_bounds)
         seed = C.c_float(d_seed) if d_seed is not None else None
         out = ResultS()
         rc = lib().ecmd_estimate_divergence(self.h, C.byref(sensor), C.byref(ev), WindowS(t0, t1), C.byref(sp),
@@ -371,7 +374,7 @@ class Context:
 
     def estimate_batched(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
                          eps: float, gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0,
-                         frontier_capacity: int = 0, d_seeds=None, polarity=None) -> list:
+                         frontier_capacity: int = 0, d_seeds=None, polarity=None, exact_bounds: bool = False) -> list:
         """B windows in one call; polarity (int8 per event, optional) selects
         the polarity-aware contrast."""
         a = _Args()
@@ -379,7 +382,7 @@ class Context:
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
         po, ptau = a.ptr(offsets, np.int64), a.ptr(tau, np.float32)
         ps = a.ptr(d_seeds, np.float32) if d_seeds is not None else None
-        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity, exact_bounds)
         out = (ResultS * max(B, 1))()
         if polarity is None:
             rc = lib().ecmd_estimate_divergence_batched(self.h, C.byref(sensor), px, py, pt, po, ptau, B,
@@ -393,15 +396,18 @@ class Context:
 
     def batch_plan(self, sensor: Sensor, d_lo: float, d_hi: float, eps: float, max_windows: int, max_events: int,
                    gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0, frontier_capacity: int = 0,
-                   max_steps: int = 0, max_records: int = 0, polarity: bool = False) -> "BatchPlan":
+                   max_steps: int = 0, max_records: int = 0, polarity: bool = False,
+                   exact_bounds: bool = False) -> "BatchPlan":
         """Device buffers for asynchronous batched searches up to the limits."""
-        return BatchPlan(self, sensor, _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity),
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity, exact_bounds)
+        return BatchPlan(self, sensor, sp,
                          PlanLimitsS(int(max_windows), int(max_steps), int(max_events), int(max_records),
                                      1 if polarity else 0, 0))
 
     def estimate_batched_noalloc(self, sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
                                  eps: float, max_events: int, out, gamma: float = 0.0, max_nodes: int = 0,
-                                 frontier_batch: int = 0, frontier_capacity: int = 0, d_seeds=None):
+                                 frontier_batch: int = 0, frontier_capacity: int = 0, d_seeds=None,
+                                 exact_bounds: bool = False):
         """The batched search on the library's static scratch (no device
         allocation): torch CUDA tensors in, results into ``out`` (a
         ``BatchPlan.result_buffer``) when the stream reaches them."""
@@ -414,7 +420,7 @@ class Context:
             raise TypeError("the allocation-free search takes device arrays")
         if out.numel() < C.sizeof(ResultS) * B:
             raise ValueError("result buffer too small")
-        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity, exact_bounds)
         rc = lib().ecmd_estimate_divergence_batched_noalloc(self.h, C.byref(sensor), C.byref(sp), *args,
                                                             C.c_void_p(out.data_ptr()))
         self._check(rc)
@@ -466,13 +472,13 @@ class Context:
 
     def estimate_learned(self, cnn: "Cnn", sensor: Sensor, x, y, t_rel, offsets, tau, d_lo: float, d_hi: float,
                          eps: float, gamma: float = 0.0, max_nodes: int = 0, frontier_batch: int = 0,
-                         frontier_capacity: int = 0) -> list:
+                         frontier_capacity: int = 0, exact_bounds: bool = False) -> list:
         """Batched estimation whose incumbents are seeded by the network."""
         a = _Args()
         B = int(tau.shape[0])
         px, py, pt = a.ptr(x, np.float32), a.ptr(y, np.float32), a.ptr(t_rel, np.float32)
         po, ptau = a.ptr(offsets, np.int64), a.ptr(tau, np.float32)
-        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity)
+        sp = _search(d_lo, d_hi, eps, gamma, max_nodes, frontier_batch, frontier_capacity, exact_bounds)
         out = (ResultS * max(B, 1))()
         rc = lib().ecmd_estimate_divergence_learned(self.h, cnn.h, C.byref(sensor), px, py, pt, po, ptau, B,
                                                     C.byref(sp), a.flags, out)

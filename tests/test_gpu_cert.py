@@ -1,0 +1,101 @@
+"""The endpoint certificate in the device search.
+
+By default a child interval whose bound value cannot matter gets the
+endpoint certificate K_bar >= U^2 - N_low^2 first, and its exact bound
+(eqs. (15)-(20)) only when that fails.  The search must expand exactly the
+nodes the all-exact search expands (ECMD_SEARCH_EXACT_BOUNDS): same
+incumbent, node, prune, point and step counts, with every child either
+certified or bounded exactly; and both must return the oracle's canonical
+optimum."""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import config_windows, pack_batch
+
+pytestmark = pytest.mark.gpu
+
+SAME = ("status", "j_star", "K", "d_hat", "nodes_expanded", "nodes_pruned", "point_evals", "steps", "seeded")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2209_13168_amd import ecmd
+
+    assert torch.cuda.is_available()
+    c = ecmd.Context(0)
+    yield c
+    c.close()
+
+
+def _sensor(spec):
+    from paper_2209_13168_amd import ecmd
+
+    return ecmd.sensor(spec.width, spec.height, spec.foe)
+
+
+CASES = [
+    ("c1", range(3), {}),
+    ("tiny", range(4), {}),
+    ("c2", range(3), {"n_events": 20_000}),
+    ("c3", range(2), {"n_events": 40_000}),
+    ("c5", range(2), {"n_events": 150_000}),
+]
+
+
+@pytest.mark.parametrize("cfg,idx,kw", CASES, ids=[c[0] for c in CASES])
+def test_certified_search_expands_the_exact_searchs_nodes(ctx, orc, cfg, idx, kw):
+    wins = config_windows(cfg, idx, **kw)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    cert = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    exact = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, exact_bounds=True)
+    for i, (a, b) in enumerate(zip(cert, exact)):
+        for f in SAME:
+            assert getattr(a, f) == getattr(b, f), (cfg, i, f, a, b)
+        assert b.bound_certs == 0
+        assert a.bound_evals + a.bound_certs == b.bound_evals, (cfg, i, a, b)
+        assert a.pixel_updates <= b.pixel_updates
+        assert a.gap == b.gap == 0.0
+        o = orc.bnb(orc.Events.of_window(wins[i]), s.d_lo, s.d_hi, s.eps)
+        assert (a.j_star, a.K) == (o.j_star, o.K), (cfg, i, a, o)
+    if cfg in ("c2", "c3", "c5"):
+        assert sum(r.bound_certs for r in cert) > 0
+
+
+def test_failed_certificates_are_bounded_exactly(ctx, orc):
+    """Events at the FOE never move (U = N_low): every certificate fails,
+    every child is bounded exactly in the same step, and the trace is the
+    exact search's (ties kept by the smaller grid index)."""
+    from synth.ventral import make_window
+
+    base = config_windows("c1", [0])[0]
+    s = base.spec
+    still = make_window(dataclasses.replace(s, n_events=0), 1, 7)
+    still = dataclasses.replace(still, x=np.full(5, s.foe[0], np.float32), y=np.full(5, s.foe[1], np.float32),
+                                t_rel=np.linspace(0, 0.4, 5).astype(np.float32), p=np.ones(5, np.int8),
+                                owner=np.full(5, -1, np.int32))
+    x, y, t, off, tau = pack_batch([still, base])
+    cert = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps)
+    exact = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, exact_bounds=True)
+    assert cert[0].bound_certs == 0 and cert[0].bound_evals == exact[0].bound_evals
+    for a, b in zip(cert, exact):
+        for f in SAME:
+            assert getattr(a, f) == getattr(b, f), (f, a, b)
+
+
+def test_certificates_off_in_paper_mode_and_with_a_budget(ctx):
+    wins = config_windows("c2", range(2), n_events=20_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    for kw in ({"gamma": 0.025}, {"max_nodes": 40}):
+        r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, **kw)
+        e = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, exact_bounds=True, **kw)
+        for a, b in zip(r, e):
+            assert a.bound_certs == 0
+            assert (a.j_star, a.K, a.gap, a.nodes_expanded, a.bound_evals) == \
+                   (b.j_star, b.K, b.gap, b.nodes_expanded, b.bound_evals)
