@@ -12,7 +12,8 @@ resident in HBM before the timed region starts.
 
 Printed: one JSON line with event-hypothesis evaluations per second (value),
 certified windows per second (batched; batched and seeded by the learned
-proposal; Algorithm 1's gamma stop with and without the seeds; the batch
+proposal; every child bounded exactly, without the endpoint certificates;
+Algorithm 1's gamma stop with and without the seeds; the batch
 handed over in host memory; the asynchronous plan replayed as a graph; plain
 one-window calls), the roofline of the hypothesis-evaluation kernel, the CPU
 oracle timed over the host cores on a bounded sample of the same windows,
@@ -79,7 +80,7 @@ TRAFFIC = {
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
                   "paper_2209_13168_amd/csrc/ecmd_api.hip")
-LEGS = ("main", "learned", "gamma", "host", "plan", "plain", "autotune")
+LEGS = ("main", "learned", "exact", "gamma", "host", "plan", "plain", "autotune")
 
 
 def log(msg: str):
@@ -228,7 +229,9 @@ def search_stats(res) -> dict:
     import numpy as np
 
     return {"nodes_expanded_mean": round(float(np.mean([r.nodes_expanded for r in res])), 2),
-            "steps_max": int(max(r.steps for r in res)), "steps_mean": round(float(np.mean([r.steps for r in res])), 2)}
+            "steps_max": int(max(r.steps for r in res)), "steps_mean": round(float(np.mean([r.steps for r in res])), 2),
+            "exact_bounds_mean": round(float(np.mean([r.bound_evals for r in res])), 2),
+            "bound_certs_mean": round(float(np.mean([r.bound_certs for r in res])), 2)}
 
 
 def cpu_baseline(batch: Batch, last, nc: int) -> dict:
@@ -362,6 +365,16 @@ def run_batch(ctx, batch: Batch, steps: int, warmup: int, fb: int, net=None, leg
         rep["windows_per_s"]["batched_learned"] = round(B / t_l, 2)
         rep["search"]["learned_seeds"] = search_stats(rl)
         log(f"{batch.cfg}: learned leg {t_l * 1e3:.1f} ms per step")
+    if "exact" in legs:
+        # every child bounded exactly (no endpoint certificates): the same
+        # nodes and result, the cost of computing every bound of Algorithm 1
+        step_plain(exact_bounds=True)
+        t_e, re_ = timed(lambda: step_plain(exact_bounds=True), max(2, reps // 2))
+        for r, a in zip(re_, last):
+            assert (r.j_star, r.K, r.nodes_expanded) == (a.j_star, a.K, a.nodes_expanded), (r, a)
+        rep["windows_per_s"]["batched_all_bounds_exact"] = round(B / t_e, 2)
+        rep["search"]["all_bounds_exact"] = search_stats(re_)
+        log(f"{batch.cfg}: all-exact leg {t_e * 1e3:.1f} ms per step")
     if "gamma" in legs:
         # Algorithm 1's stop at a gap of gamma contrast units (Sec. 6): the
         # result is within gamma of the optimum, no longer the canonical one

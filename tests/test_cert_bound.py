@@ -5,9 +5,12 @@ pixels alone, U = sum over the events inside the image at both ends of
 |dkx| + |dky| + 1 and claims K_bar >= U^2 - N_low^2 (eqs. (15)-(20)): such an
 event's staircase walk visits at least that many distinct image pixels, so
 U <= sum of the bound image, and Cauchy-Schwarz over the M cells gives
-M * S_bar >= (sum H_bar)^2.  These tests take the endpoint pixels from the
-independent NumPy warp and the bound image from the oracle, and check every
-link of that chain, on every depth of the grid and on single events.
+M * S_bar >= (sum H_bar)^2.  With the point values (S_e, N_e) at an end d_e
+of the interval it also claims K_bar >= M S_e + max(0, U - N_e)^2 - N_low^2:
+H_bar >= H(d_e) pixel by pixel, so S_bar >= S_e + (sum (H_bar - H(d_e)))^2 / M.
+These tests take the endpoint pixels from the independent NumPy warp and the
+bound and point images from the oracle, and check every link of both chains,
+on every depth of the grid and on single events.
 """
 
 import numpy as np
@@ -49,7 +52,15 @@ def test_certificate_is_below_the_bound(orc, k):
             assert N == int(full.sum())  # N_low: both endpoints inside (eq. (20))
             assert U <= int(img.sum(dtype=np.int64))  # each such walk visits |dkx| + |dky| + 1 image pixels
             assert ev.M * S >= int(img.sum(dtype=np.int64)) ** 2  # Cauchy-Schwarz
-            assert orc.key(ev.M, S, N) >= U * U - N * N, (depth, j)
+            Kb = orc.key(ev.M, S, N)
+            assert Kb >= U * U - N * N, (depth, j)
+            # either end d_e of the interval: H_bar >= H(d_e) pixel by pixel
+            for d_e in (d_a, d_b):
+                Se, Ne, He = orc.point(ev, d_e, want_image=True)
+                assert np.all(img >= He)
+                X = max(0, U - Ne)  # sum(H_bar - H(d_e)) >= U - N_e
+                assert ev.M * S >= ev.M * Se + X * X
+                assert Kb >= ev.M * Se + X * X - N * N, (depth, j, d_e)
 
 
 def test_single_event_walk_visits_at_least_its_manhattan_length(orc):
