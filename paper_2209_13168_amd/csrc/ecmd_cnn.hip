@@ -181,6 +181,84 @@ __global__ __launch_bounds__(kThreads) void k_cnn(const float* __restrict__ P, c
     conv_wgrad<1, 16, 64>(img, a1, gp + oW1, gp + oB1, false);
 }
 
+// Forward pass alone (the proposal of the learned incumbent), for a few
+// images at a time: 1024 threads per image so that a batch of a few dozen
+// windows is not bound by one wave per SIMD.  Each wave computes CB output
+// channels (wave-uniform, so their weights are scalar loads) at every
+// position it owns, reusing each input read for the CB channels; a layer
+// whose output feeds a rounded input stores it rounded (bf(bf(v)) = bf(v)).
+// Every output sums its products in the order of conv_fwd, so the results
+// are conv_fwd's.
+constexpr int kFwdThreads = 1024;
+constexpr int kFwdWaves = kFwdThreads / 64;
+
+template <int CI, int CO, int HI, int CB>
+__device__ void conv_fwd_waves(const float* __restrict__ in, float* __restrict__ out, const float* __restrict__ W,
+                               const float* __restrict__ b, bool round_out) {
+    constexpr int HO = HI / 2, NP = HO * HO;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int o0 = wave * CB; o0 < CO; o0 += kFwdWaves * CB) {
+        for (int p = lane; p < NP; p += 64) {
+            const int y = p / HO, x = p % HO;
+            float acc[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+            for (int i = 0; i < CI; ++i) {
+                const float* ini = in + i * HI * HI;
+                for (int ky = 0; ky < 3; ++ky) {
+                    const int iy = 2 * y + ky - 1;
+                    if (iy < 0 || iy >= HI) continue;
+                    for (int kx = 0; kx < 3; ++kx) {
+                        const int ix = 2 * x + kx - 1;
+                        if (ix < 0 || ix >= HI) continue;
+                        const float v = ini[iy * HI + ix];
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) acc[c] = fmaf(bf(W[((o0 + c) * CI + i) * 9 + ky * 3 + kx]), v, acc[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const float r = fmaxf(acc[c] + b[o0 + c], 0.0f);
+                out[(o0 + c) * NP + p] = round_out ? bf(r) : r;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kFwdThreads) void k_cnn_fwd(const float* __restrict__ P,
+                                                         const uint16_t* __restrict__ imgs, int B,
+                                                         float* __restrict__ out) {
+    extern __shared__ float s[];
+    const int b = blockIdx.x;
+    if (b >= B) return;
+    const int tid = threadIdx.x;
+    float* img = s + sImg;
+    float* a1 = s + sA1;
+    float* a2 = s + sA2;
+    float* a3 = s + sA3;
+    float* g = s + sG;
+    for (int k = tid; k < 64 * 64; k += kFwdThreads) img[k] = bits_to_f(imgs[(long long)b * 4096 + k]);
+    __syncthreads();
+    conv_fwd_waves<1, 16, 64, 1>(img, a1, P + oW1, P + oB1, true);
+    __syncthreads();
+    conv_fwd_waves<16, 32, 32, 2>(a1, a2, P + oW2, P + oB2, true);
+    __syncthreads();
+    conv_fwd_waves<32, 64, 16, 4>(a2, a3, P + oW3, P + oB3, false);
+    __syncthreads();
+    if (tid < 64) {
+        float acc = 0.0f;
+        for (int p = 0; p < 64; ++p) acc += a3[tid * 64 + p];
+        g[tid] = bf(acc * (1.0f / 64.0f)) * bf(P[oWfc + tid]);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        float d = 0.0f;
+        for (int c = 0; c < 64; ++c) d += g[c];
+        out[b] = d + P[oBfc];
+    }
+}
+
 // grad[p] = sum_b pg[b][p] (fixed order); loss = sum_b lossb[b]
 __global__ void k_cnn_reduce(const float* __restrict__ pg, const float* __restrict__ lossb, int B,
                              float* __restrict__ grad, float* __restrict__ loss) {
@@ -222,13 +300,20 @@ size_t cnn_lds_bytes() { return (size_t)kLdsFloats * sizeof(float); }
 int cnn_nparam() { return kNParam; }
 
 hipError_t cnn_set_lds() {
-    return hipFuncSetAttribute((const void*)k_cnn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnn_lds_bytes());
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_cnn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cnn_lds_bytes());
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_cnn_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)cnn_lds_bytes());
 }
 
 hipError_t launch_cnn(hipStream_t s, const float* P, const uint16_t* imgs, int B, float* out, int mode,
                       const float* labels, float* pg, float* lossb) {
     if (B <= 0) return hipSuccess;
-    k_cnn<<<B, kThreads, cnn_lds_bytes(), s>>>(P, imgs, B, out, mode, labels, 1.0f / (float)B, pg, lossb);
+    if (mode == 0)
+        k_cnn_fwd<<<B, kFwdThreads, cnn_lds_bytes(), s>>>(P, imgs, B, out);
+    else
+        k_cnn<<<B, kThreads, cnn_lds_bytes(), s>>>(P, imgs, B, out, mode, labels, 1.0f / (float)B, pg, lossb);
     return hipGetLastError();
 }
 
