@@ -495,6 +495,10 @@ size_t eval_lds_bytes(int ring_px) {
 // that return nothing, then removes the border counters' share and sums the
 // squares of the tile's counters in one 16-byte-wide pass that also zeroes
 // them for the next hypothesis (the tile region is cleared once, at start).
+// An interval takes the segment's owned events, then its guest copies,
+// skipping a guest whose walk box misses the tile (all its increments would
+// land on the border).  An endpoint certificate reads the owned events only
+// and touches no counter.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
@@ -649,27 +653,49 @@ __global__ __launch_bounds__(NT) void k_eval(
                 tile_add(org, R, kxa, kya);
                 if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
             };
-            // two events in flight ahead of the one being binned (the
-            // loads may read up to two strides past the segment: the store is
-            // padded by kEvalPad records)
-            unsigned i = tid;
-            if (i < nseg) {
-                float4 e0 = at(i), e1 = at(i + NT), e2;
-                for (;;) {
-                    e2 = at(i + 2 * NT);
-                    one(e0, i);
-                    i += NT;
-                    if (i >= nseg) break;
-                    e0 = at(i + 2 * NT);
-                    one(e1, i);
-                    i += NT;
-                    if (i >= nseg) break;
-                    e1 = at(i + 2 * NT);
-                    one(e2, i);
-                    i += NT;
-                    if (i >= nseg) break;
+            // Owned events first (N_low counts them), then the guest copies:
+            // a guest whose walk box for this interval misses the tile would
+            // only increment the discarded border, so it is skipped (and its
+            // increments are not counted).  Two events in flight ahead of the
+            // one being binned (the loads may read up to two strides past a
+            // range: the store is padded by kEvalPad records).
+            unsigned skipped = 0;
+            const int gx1 = x0 + tw - 1, gy1 = y0 + th - 1;
+            const auto guest = [&](const float4& e, unsigned i) {
+                const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
+                const int kxb = flr_clamp(fmaf(e.z, rb, e.x), g.W), kyb = flr_clamp(fmaf(e.w, rb, e.y), g.H);
+                const bool miss = max(kxa, kxb) < x0 || min(kxa, kxb) > gx1 || max(kya, kyb) < y0 || min(kya, kyb) > gy1;
+                if (miss) {
+                    skipped += 1;
+                } else {
+                    tile_add(org, R, kxa, kya);
+                    if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
                 }
-            }
+            };
+            const auto run = [&](unsigned i, unsigned lim, auto&& f) {
+                if (i < lim) {
+                    float4 e0 = at(i), e1 = at(i + NT), e2;
+                    for (;;) {
+                        e2 = at(i + 2 * NT);
+                        f(e0, i);
+                        i += NT;
+                        if (i >= lim) break;
+                        e0 = at(i + 2 * NT);
+                        f(e1, i);
+                        i += NT;
+                        if (i >= lim) break;
+                        e1 = at(i + 2 * NT);
+                        f(e2, i);
+                        i += NT;
+                        if (i >= lim) break;
+                    }
+                }
+            };
+            run((unsigned)tid, nown, one);
+            run(nown + (unsigned)tid, nseg, guest);
+            // start pixels: this thread's owned events and guests, less the skipped guests
+            visits = ((unsigned)tid < nown ? (nown - 1u - (unsigned)tid) / NT + 1u : 0u) +
+                     (nown + (unsigned)tid < nseg ? (nseg - 1u - nown - (unsigned)tid) / NT + 1u : 0u) - skipped;
             visits += acc.visits;
             nlow = nlow32;
         }
