@@ -105,16 +105,20 @@ typedef struct {
  *
  * flags: ECMD_SEARCH_EXACT_BOUNDS computes the bound of eqs. (15)-(20) for
  * every child interval.  Without it (the default), a child whose decision
- * cannot depend on its bound's value (gamma = 0, no node budget, and every
- * node the queue can hold after this step is expanded next) is first given
+ * cannot depend on its bound's value (no node budget, and every node the
+ * queue can hold after this step is expanded next) is first given
  * a cheaper certificate from its endpoints alone: with U the sum over the
  * owned events with both endpoints in the image of |dkx| + |dky| + 1 (the
  * walk visits that many distinct image pixels), Cauchy-Schwarz over the M
  * cells gives M * S_bar >= U^2, so K_bar >= U^2 - N_low^2.  When that
  * exceeds the incumbent the node is kept, the decision the exact bound
- * gives; otherwise the exact bound is computed in the same step.  The nodes
- * expanded, the incumbent and the result are those of the exact search;
- * bound_evals and pixel_updates count exact bounds only. */
+ * gives; otherwise the exact bound is computed in the same step.  With
+ * gamma = 0 the nodes expanded, the incumbent and the result are those of
+ * the exact search.  With gamma > 0 the stop test bounds a certified node's
+ * points by the exact bound of its nearest exactly bounded ancestor (an
+ * interval containing them), which is looser: the search stops at the same
+ * step as the exact search or later, with the same guarantee.  bound_evals
+ * and pixel_updates count exact bounds only. */
 #define ECMD_SEARCH_EXACT_BOUNDS 1u
 
 typedef struct {
@@ -135,7 +139,8 @@ typedef struct {
  * count (exact bounds and points); pixel_updates = upper-bound image
  * increments; bound_certs = child intervals kept on the endpoint certificate
  * (see ecmd_search.flags), whose walks were not made.  A search cut short
- * while such a node is queued reports gap = infinity. */
+ * while such a node is queued takes that node's gap from its nearest
+ * exactly bounded ancestor (infinity when it has none). */
 typedef struct {
     int32_t status;
     uint32_t j_star;

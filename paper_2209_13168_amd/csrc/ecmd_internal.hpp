@@ -52,7 +52,8 @@ struct Node {
     long long khi;
     unsigned ja, jb;  // grid interval [ja, jb]; jb carries kNodeCert
     float lc;         // expected endpoint certificate of this node's children
-    unsigned pad;
+    float ub;         // with kNodeCert: an upper bound of K at every grid point of the node (an
+                      // ancestor's exact bound, rounded up; infinity when no ancestor has one)
 };
 
 // Set in Node::jb when the key is the endpoint certificate (a lower bound of
@@ -65,6 +66,7 @@ constexpr long long kNodeRepair = (long long)(-0x7fffffffffffffffll - 1);
 struct Sel {
     unsigned ja, jb, jc, kids;  // expanded node, its centre, 1 if it has children
     float lc;                   // expected endpoint certificate of its children (Node::lc)
+    float ub;                   // upper bound of K at the node's grid points (Node::ub)
 };
 
 struct Geometry {

@@ -74,6 +74,21 @@ __device__ __forceinline__ double i128_to_double(i128 v) {
     return neg ? -r : r;
 }
 
+// A float no smaller than v >= 0 (the double is within 2^-53 of v, the
+// float within 2^-24 of the double, the factor covers both).
+__device__ __forceinline__ float ub_float(i128 v) { return (float)(i128_to_double(v) * (1.0 + 0x1p-20)); }
+
+// The smallest integer no smaller than the finite f >= 0.
+__device__ __forceinline__ i128 ceil_i128(float f) {
+    int e;
+    const float m = frexpf(f, &e);  // f = m 2^e, m in [0.5, 1)
+    const long long mi = (long long)ldexpf(m, 24);  // f = mi 2^(e - 24) exactly
+    const int sh = e - 24;
+    if (sh >= 0) return (i128)mi << sh;
+    if (sh < -24) return mi > 0 ? (i128)1 : (i128)0;
+    return ((i128)mi + (((i128)1 << -sh) - 1)) >> -sh;
+}
+
 __device__ __forceinline__ bool improvable(i128 key, unsigned ja, i128 Kinc, unsigned jinc) {
     return key > Kinc || (key == Kinc && (unsigned long long)ja + 1ull < (unsigned long long)jinc);
 }
@@ -429,6 +444,18 @@ __device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, i
 
 __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, int ky, int kxb,
                                           int kyb, float xf, float yf, float axf, float ayf, WalkAcc& acc) {
+    // a single step along a row or a column (|dx| + |dy| = 1, i.e.
+    // dx^2 + dy^2 = 1) has no corner to test: it visits the end pixel only
+    // (the coordinates are clamped to [-1, W] x [-1, H], so the squares are
+    // 24-bit products)
+    {
+        const int dx = kxb - kx, dy = kyb - ky;
+        if (__mul24(dx, dx) + __mul24(dy, dy) == 1) {
+            acc.visits += 1u;
+            tile_add(org, R, kxb, kyb);
+            return;
+        }
+    }
     // step direction of each coordinate (not used once it is at its end)
     const bool px = kxb > kx, py = kyb > ky;
     const int sx = px ? 1 : -1, sy = py ? 1 : -1;
@@ -929,16 +956,16 @@ __device__ void emit_items(const Search& sp, int w, const int* tiles, int nt, in
 // Hypotheses of the selected nodes, the list of active slots, and the work
 // items.  q_rem: nodes left in the queue; n_kids: selected nodes with
 // children.  When every node the queue can hold after the next step is
-// expanded at that step (q_rem + 2 n_kids <= F), gamma is 0 and there is no
-// node budget, a child's bound value decides nothing but whether it is
-// kept, so the children get the endpoint certificate (exact bounds when it
-// fails, in the same step).
+// expanded at that step (q_rem + 2 n_kids <= F) and there is no node
+// budget, a child's bound value decides nothing but whether it is kept, so
+// the children get the endpoint certificate (exact bounds when it fails, in
+// the same step).  For the gamma stop a certified child's points are
+// bounded by its nearest exactly bounded ancestor's bound instead.
 __device__ void emit_hyps(const Search& sp, const WinParam& p, int w, int T, const int* tiles, int nt,
                           const Sel* sl, int n_sel, int q_rem, int n_kids, float kinc, Hyp* hy, int* act,
                           Item* items, int qcap, Queue* qf, int* s_wave) {
     const int F = sp.F, HS = sp.HS;
-    const bool cert = sp.cert && sp.gamma_key < 0 && sp.max_nodes == 0 && q_rem + 2 * n_kids <= F &&
-                      q_rem + 2 * n_kids <= sp.CAP;
+    const bool cert = sp.cert && sp.max_nodes == 0 && q_rem + 2 * n_kids <= F && q_rem + 2 * n_kids <= sp.CAP;
     // a node's children take the certificate when it is expected to clear
     // the incumbent K_inc (kinc): a failed certificate costs its pass and the
     // exact bound (measured on the three batches: margins of 0.5 to 1.5 x
@@ -1025,6 +1052,7 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
         root.jc = top >> 1;
         root.kids = (top >= 4) ? 1u : 0u;
         root.lc = INFINITY;  // no evaluation yet: the root's children try the certificate
+        root.ub = INFINITY;  // and no bound above them
         sl[0] = root;
         int n_sel = 1;
         if (seeds) {
@@ -1039,6 +1067,7 @@ __global__ __launch_bounds__(NTF) void k_init(Search sp, const WinParam* __restr
                     sd.ja = sd.jb = sd.jc = (unsigned)j;
                     sd.kids = 0;
                     sd.lc = 0.0f;
+                    sd.ub = INFINITY;
                     sl[1] = sd;
                     n_sel = 2;
                 }
@@ -1163,7 +1192,7 @@ __global__ __launch_bounds__(NTF) void k_frontier_a(
             const Sel x = sl[c >> 1];
             nd.ja = (c & 1) ? x.jc : x.ja;
             nd.jb = (c & 1) ? x.jb : x.jc;
-            nd.pad = 0;
+            nd.ub = x.ub;  // every grid point of the child is one of the parent's
             if (hy[F + c].kind == HYP_CERT) {
                 // S holds U (walk pixels of the events inside at both ends),
                 // a lower bound of sum H_bar.  Two lower bounds of K_bar:
@@ -1243,7 +1272,7 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
     __shared__ unsigned s_j[NTF];
     __shared__ int s_wave[NWF], s_tiles[kMaxTiles], s_nt;
     __shared__ int s_hist[130];
-    __shared__ int s_bstar, s_quota, s_stop, s_take, s_anycert;
+    __shared__ int s_bstar, s_quota, s_stop, s_take, s_anycert, s_ubmax;
     __shared__ unsigned long long s_pix;
     __shared__ long long s_nbound, s_pruned;
     if (tid == 0) s = st[w];
@@ -1264,6 +1293,7 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
         s_nbound = 0;
         s_pruned = 0;
         s_anycert = 0;
+        s_ubmax = 0;  // 0.0f
     }
     for (int b = tid; b < 130; b += NTF) s_hist[b] = 0;
     __syncthreads();
@@ -1293,8 +1323,10 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
     // (3) which queued nodes can still improve; histogram of their gap
     // sizes; the node Algorithm 1 would pop next (largest bound, ties to the
     // smaller grid index; queued intervals are disjoint, so ja names it).
-    // A certificate key is only a lower bound of K_bar, so while such a node
-    // is queued no finite gap is certified.
+    // A certificate key is only a lower bound of K_bar: such a node's points
+    // are bounded above by its ub (an ancestor's exact bound), and the gap
+    // certified while it is queued is taken from that (infinite when some
+    // such node has no exactly bounded ancestor).
     i128 best_gap = -1;
     unsigned best_ja = 0xFFFFFFFFu;
     for (int i = tid; i < n; i += NTF) {
@@ -1303,7 +1335,10 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
         if (improvable(k, nd.ja, Kinc, jinc)) {
             const i128 gap = k - Kinc;
             atomicAdd(&s_hist[bitlen128(gap)], 1);
-            if (nd.jb & kNodeCert) s_anycert = 1;
+            if (nd.jb & kNodeCert) {
+                s_anycert = 1;
+                atomicMax(&s_ubmax, __float_as_int(nd.ub));  // ub >= 0: int order is float order
+            }
             if (gap > best_gap || (gap == best_gap && nd.ja < best_ja)) {
                 best_gap = gap;
                 best_ja = nd.ja;
@@ -1323,7 +1358,18 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
         s.nodes_pruned += s_pruned;
         // the gap certified so far (queued and selected nodes), kept for a
         // search that is cut short after this step (-1: none certified)
-        sp128(s_anycert ? (i128)-1 : best_gap < 0 ? (i128)0 : best_gap, s.gap_hi, s.gap_lo);
+        i128 gap = best_gap < 0 ? (i128)0 : best_gap;
+        bool gap_inf = false;
+        if (s_anycert) {
+            const float u = __int_as_float(s_ubmax);
+            if (!(u < INFINITY)) {
+                gap_inf = true;
+            } else {
+                const i128 g = ceil_i128(u) - Kinc;
+                if (g > gap) gap = g;
+            }
+        }
+        sp128(gap_inf ? (i128)-1 : gap, s.gap_hi, s.gap_lo);
         int stop = 0;
         if (overflow) {
             s.status = -5;  // ECMD_EFRONTIER
@@ -1334,9 +1380,9 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
             s.gap_hi = 0;
             s.gap_lo = 0;
             stop = 1;
-        } else if (sp.gamma_key >= 0 && best_gap <= (i128)sp.gamma_key) {
+        } else if (sp.gamma_key >= 0 && !gap_inf && gap <= (i128)sp.gamma_key) {
             s.status = 0;
-            sp128(best_gap, s.gap_hi, s.gap_lo);
+            sp128(gap, s.gap_hi, s.gap_lo);
             s.nodes_pruned += n_keep;
             stop = 1;
         }
@@ -1417,6 +1463,7 @@ __global__ __launch_bounds__(NTF) void k_frontier_b(
             x.jc = (nd.ja + jb) >> 1;
             x.kids = kids ? 1u : 0u;
             x.lc = nd.lc;
+            x.ub = (nd.jb & kNodeCert) ? nd.ub : ub_float(mk128(nd.khi, nd.klo));
             sl[nsel + rt] = x;
         }
         out += tot_k;

@@ -91,14 +91,42 @@ def test_failed_certificates_are_bounded_exactly(ctx, orc):
         assert a.bound_evals + a.bound_certs == b.bound_evals
 
 
-def test_certificates_off_in_paper_mode_and_with_a_budget(ctx):
+def test_certificates_off_with_a_budget(ctx):
+    """A node budget can stop the search at any step, so every child is
+    bounded exactly: the trace is the all-exact search's."""
     wins = config_windows("c2", range(2), n_events=20_000)
     s = wins[0].spec
     x, y, t, off, tau = pack_batch(wins)
-    for kw in ({"gamma": 0.025}, {"max_nodes": 40}):
-        r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, **kw)
-        e = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, exact_bounds=True, **kw)
-        for a, b in zip(r, e):
-            assert a.bound_certs == 0
-            assert (a.j_star, a.K, a.gap, a.nodes_expanded, a.bound_evals) == \
-                   (b.j_star, b.K, b.gap, b.nodes_expanded, b.bound_evals)
+    r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, max_nodes=40)
+    e = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, exact_bounds=True, max_nodes=40)
+    for a, b in zip(r, e):
+        assert a.bound_certs == 0
+        assert (a.j_star, a.K, a.gap, a.nodes_expanded, a.bound_evals) == \
+               (b.j_star, b.K, b.gap, b.nodes_expanded, b.bound_evals)
+
+
+@pytest.mark.parametrize("gamma", [0.025, 0.002])
+def test_certificates_in_paper_mode(ctx, orc, gamma):
+    """Algorithm 1's gamma stop with certified children: a certified node's
+    points are bounded by its nearest exactly bounded ancestor's bound, so
+    the stop is conservative.  Every window's result is within gamma of the
+    oracle's optimum, its reported gap covers the true one and is within
+    gamma, its key is the oracle's key at the returned point, and it never
+    expands fewer nodes than the all-exact gamma search (whose stop sees
+    every queued bound exactly)."""
+    wins = config_windows("c2", range(4), n_events=40_000)
+    s = wins[0].spec
+    M2 = float(s.width * s.height) ** 2
+    x, y, t, off, tau = pack_batch(wins)
+    r = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, gamma=gamma)
+    e = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, gamma=gamma, exact_bounds=True)
+    assert sum(a.bound_certs for a in r) > 0
+    for w, a, b in zip(wins, r, e):
+        ev = orc.Events.of_window(w)
+        o = orc.bnb(ev, s.d_lo, s.d_hi, s.eps)
+        assert a.status == 0 and b.status == 0
+        assert (o.K - a.K) / M2 <= gamma + 1e-12, (a, o)
+        assert a.gap <= gamma and a.gap * M2 >= (o.K - a.K) - 1e-9 * M2, (a, o)
+        S, N = orc.point(ev, a.d_hat)
+        assert orc.key(ev.M, S, N) == a.K
+        assert b.bound_certs == 0 and a.nodes_expanded >= b.nodes_expanded, (a, b)
