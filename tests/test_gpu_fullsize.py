@@ -32,7 +32,7 @@ def _golden(cfg):
     return {r["window"]: r for r in rows if r["config"] == cfg}
 
 
-def _run(ctx, cfg, B):
+def _run(ctx, cfg, B, **kw):
     import torch
 
     from paper_2209_13168_amd import ecmd
@@ -53,7 +53,7 @@ def _run(ctx, cfg, B):
     s = config_specs(cfg, 0)
     print(f"{cfg}: {B} windows, {int(off[-1])} events", flush=True)
     res = ctx.estimate_batched(ecmd.sensor(s.width, s.height, s.foe), *args, torch.from_numpy(off).to(dev),
-                               torch.from_numpy(np.concatenate(taus)).to(dev), s.d_lo, s.d_hi, s.eps)
+                               torch.from_numpy(np.concatenate(taus)).to(dev), s.d_lo, s.d_hi, s.eps, **kw)
     return res, s, off
 
 
@@ -85,6 +85,35 @@ def test_full_640x480_batch(ctx, orc):
 
 def test_full_1280x720_batch_with_hot_pixels(ctx, orc):
     _check(ctx, orc, "c5", 256, 3)
+
+
+def test_gamma_stop_on_the_1280x720_batch(ctx, orc):
+    """Algorithm 1's gamma = 0.025 stop (Sec. 6) on the whole 256-window
+    1280x720 batch, with the endpoint certificates on: on the windows with a
+    stored oracle optimum the result is within gamma of it and the reported
+    gap covers the true one; on every window the result is within its own
+    reported gap (at most gamma) of the canonical search's optimum on the
+    same batch, and on two sampled windows its key is the oracle's key at
+    the returned point."""
+    cfg, B, gamma = "c5", 256, 0.025
+    res, s, off = _run(ctx, cfg, B, gamma=gamma)
+    ref, _, _ = _run(ctx, cfg, B)
+    M2 = float(s.width * s.height) ** 2
+    assert all(r.status == 0 for r in res)
+    assert sum(r.bound_certs for r in res) > 0
+    for k, g in _golden(cfg).items():
+        lost = (int(g["K"]) - res[k].K) / M2
+        assert 0.0 <= lost <= gamma and res[k].gap >= lost - 1e-12, (k, res[k], g)
+    for a, b in zip(res, ref):
+        assert a.gap <= gamma and a.K <= b.K and (b.K - a.K) / M2 <= a.gap + 1e-12, (a, b)
+        assert a.nodes_expanded <= b.nodes_expanded
+    from synth import config_windows
+
+    L = res[0].L
+    for k in [int(i) for i in np.argsort(np.diff(off))[:2]]:
+        ev = orc.Events.of_window(config_windows(cfg, [k])[0])
+        S, N = orc.point(ev, orc.grid_d(s.d_lo, s.d_hi, L, res[k].j_star))
+        assert orc.key(ev.M, S, N) == res[k].K, (cfg, k)
 
 
 def test_images_on_the_1280x720_tiling_with_hot_pixels(ctx, orc):
