@@ -123,8 +123,10 @@ def parse():
                     help="Algorithm 1's stop gap (contrast units) of the gamma legs (Sec. 6 uses 0.025)")
     ap.add_argument("--cpu-windows", type=int, default=None, help="oracle sample size (smallest windows)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_13168_amd", "weights", "cnn_c2.npz"),
-                    help="trained proposal network of the learned legs")
+    ap.add_argument("--weights", default=None,
+                    help="trained proposal network of the learned legs (default: the one trained for the main "
+                         "batch's sensor, paper_2209_13168_amd/weights/cnn_c2.npz for 346x260 and 640x480, "
+                         "cnn_c5.npz for 1280x720)")
     ap.add_argument("--print-sources-sha", action="store_true", help="print the kernel sources hash and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer three times (to scale HBM byte counters)")
@@ -486,6 +488,9 @@ def main():
 
     ctx = ecmd.Context(0)
     net = None
+    if args.weights is None:
+        args.weights = os.path.join(ROOT, "paper_2209_13168_amd", "weights",
+                                    "cnn_c5.npz" if args.config == "c5" else "cnn_c2.npz")
     if os.path.exists(args.weights) and ({"learned", "gamma", "autotune"} & set(legs)):
         from paper_2209_13168_amd import learned
 

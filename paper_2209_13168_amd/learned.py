@@ -1,14 +1,20 @@
 """Training and evaluation driver of the learned incumbent.
 
-Data: windows of the 346x260 generator (100k events, true D ~ U(0.05, 0.8)),
-drawn on the host cores; each window's 64x64 input image comes from the
-library's downsample kernel and its label is the certified branch-and-bound
-optimum d_hat from the library (the network learns to propose the BnB's own
-answer).  Training runs the library's forward/backward/Adam kernels.
+One network per sensor.  Data: windows of that sensor's generator, drawn on
+the host cores -- for 346x260 the 100k-event generator with true D ~
+U(0.05, 0.8); for 1280x720 the stress generator (0.1-5M events, 0.1% hot
+pixels, D in [0, 2]) at window indices from TRAIN_BASE on, so that the
+benchmark's windows 0-255 stay held out.  Each window's 64x64 input image
+comes from the library's downsample kernel and its label is the certified
+branch-and-bound optimum d_hat from the library (the network learns to
+propose the BnB's own answer).  Training runs the library's
+forward/backward/Adam kernels.
 
-    python -m paper_2209_13168_amd.learned train --windows 20000 \
+    python -m paper_2209_13168_amd.learned train --config c2 --windows 20000 \
         --out paper_2209_13168_amd/weights/cnn_c2.npz
-    python -m paper_2209_13168_amd.learned eval --weights ... --windows 256
+    python -m paper_2209_13168_amd.learned train --config c5 --windows 6000 \
+        --out paper_2209_13168_amd/weights/cnn_c5.npz
+    python -m paper_2209_13168_amd.learned eval --config c5 --weights ... --eval-windows 256
 """
 
 from __future__ import annotations
@@ -28,7 +34,8 @@ if ROOT not in sys.path:
 
 from paper_2209_13168_amd import ecmd  # noqa: E402
 
-HELD_OUT = 1_000_000  # window indices from here on are never trained on
+HELD_OUT = 1_000_000  # 346x260 generator: window indices from here on are never trained on
+TRAIN_BASE = 100_000  # 1280x720: training windows start here (the benchmark uses 0-255)
 
 
 def _gen(args):
@@ -55,31 +62,40 @@ def windows_chunks(indices, cfg="c4", n_events=None, chunk=256, procs=None):
 
 SEARCH = dict(d_lo=0.0, d_hi=1.5, eps=1e-5)
 SENSOR = (346, 260, (173.0, 130.0))
+# per sensor: (generator, first training window, first held-out window, sensor, search)
+SETUPS = {
+    "c2": ("c4", 0, HELD_OUT, SENSOR, SEARCH),
+    "c5": ("c5", TRAIN_BASE, 0, (1280, 720, (640.0, 360.0)), dict(d_lo=0.0, d_hi=2.0, eps=1e-5)),
+}
 
 
-def label_chunk(ctx, x, y, t, offs, tau, device=True, seeds=None, net=None):
+def label_chunk(ctx, x, y, t, offs, tau, device=True, seeds=None, net=None, setup="c2"):
     """Downsampled images (GPU) and certified optima (GPU BnB) of a chunk."""
     import torch
 
-    sen = ecmd.sensor(*SENSOR)
+    _, _, _, sensor, search = SETUPS[setup]
+    sen = ecmd.sensor(*sensor)
     if device:
         dev = torch.device("cuda:0")
         x, y, t, offs, tau = (torch.from_numpy(a).to(dev) for a in (x, y, t, offs, tau))
     imgs = ctx.downsample(sen, x, y, offs)
     if net is not None:
-        res = ctx.estimate_learned(net, sen, x, y, t, offs, tau, **SEARCH)
+        res = ctx.estimate_learned(net, sen, x, y, t, offs, tau, **search)
     else:
-        res = ctx.estimate_batched(sen, x, y, t, offs, tau, **SEARCH, d_seeds=seeds)
+        res = ctx.estimate_batched(sen, x, y, t, offs, tau, **search, d_seeds=seeds)
     if device:
         imgs = imgs.cpu().numpy().view(np.uint16)
     return imgs.reshape(-1, 64 * 64), res
 
 
-def build_dataset(ctx, indices, n_events=None, log=print):
+def build_dataset(ctx, indices, n_events=None, log=print, setup="c2"):
+    gen, base = SETUPS[setup][:2]
     imgs, labels, truth = [], [], []
     t0 = time.time()
-    for x, y, t, offs, tau, dt in windows_chunks(list(indices), n_events=n_events):
-        im, res = label_chunk(ctx, x, y, t, offs, tau)
+    chunk = 256 if setup == "c2" else 64
+    for x, y, t, offs, tau, dt in windows_chunks([base + int(k) for k in indices], cfg=gen, n_events=n_events,
+                                                 chunk=chunk):
+        im, res = label_chunk(ctx, x, y, t, offs, tau, setup=setup)
         imgs.append(im)
         labels.append(np.array([r.d_hat for r in res], np.float32))
         truth.append(dt)
@@ -123,18 +139,23 @@ def load(ctx, path):
     return net, json.loads(str(z["meta"]))
 
 
-def evaluate(ctx, net, n_windows=256, n_events=None, log=print):
+def evaluate(ctx, net, n_windows=256, n_events=None, log=print, setup="c2", label_mean=0.425):
     """Network error against the BnB optimum, and the search with and
-    without the network's seeds on held-out windows."""
+    without the network's seeds on held-out windows (label_mean: the
+    training labels' mean, the constant predictor compared against; 0.425
+    is the mean of U(0.05, 0.8))."""
+    gen, _, held = SETUPS[setup][:3]
     err, err_mean, plain_nodes, seeded_nodes, plain_steps, seeded_steps = [], [], [], [], [], []
     same = True
-    for x, y, t, offs, tau, dt in windows_chunks(list(range(HELD_OUT, HELD_OUT + n_windows)), n_events=n_events):
-        im, plain = label_chunk(ctx, x, y, t, offs, tau)
-        _, seeded = label_chunk(ctx, x, y, t, offs, tau, net=net)
+    chunk = 256 if setup == "c2" else 64
+    for x, y, t, offs, tau, dt in windows_chunks(list(range(held, held + n_windows)), cfg=gen, n_events=n_events,
+                                                 chunk=chunk):
+        im, plain = label_chunk(ctx, x, y, t, offs, tau, setup=setup)
+        _, seeded = label_chunk(ctx, x, y, t, offs, tau, net=net, setup=setup)
         pred = net.forward(im)
         lab = np.array([r.d_hat for r in plain])
         err.append(np.abs(pred - lab))
-        err_mean.append(np.abs(0.425 - lab))  # the label mean of U(0.05, 0.8)
+        err_mean.append(np.abs(label_mean - lab))
         plain_nodes += [r.nodes_expanded for r in plain]
         seeded_nodes += [r.nodes_expanded for r in seeded]
         plain_steps += [r.steps for r in plain]
@@ -159,27 +180,35 @@ def evaluate(ctx, net, n_windows=256, n_events=None, log=print):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--config", choices=sorted(SETUPS), default="c2", help="sensor: c2 = 346x260, c5 = 1280x720")
     ap.add_argument("--windows", type=int, default=20000)
-    ap.add_argument("--events", type=int, default=0, help="events per window (0 = 100k)")
+    ap.add_argument("--events", type=int, default=0, help="events per window (0 = the generator's)")
     ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "weights", "cnn_c2.npz"))
-    ap.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "weights", "cnn_c2.npz"))
+    ap.add_argument("--out", default=None, help="default: weights/cnn_<config>.npz")
+    ap.add_argument("--weights", default=None, help="default: weights/cnn_<config>.npz")
     ap.add_argument("--eval-windows", type=int, default=256)
     a = ap.parse_args()
+    path = os.path.join(os.path.dirname(__file__), "weights", f"cnn_{a.config}.npz")
     ctx = ecmd.Context(0)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if a.cmd == "train":
-        imgs, labels, truth = build_dataset(ctx, range(a.windows), n_events=a.events or None, log=log)
+        imgs, labels, truth = build_dataset(ctx, range(a.windows), n_events=a.events or None, log=log,
+                                            setup=a.config)
         log(f"label vs true D: mean abs {np.abs(labels - truth).mean():.4f}")
         net, hist = train(ctx, imgs, labels, epochs=a.epochs, log=log)
-        meta = {"windows": int(a.windows), "events": a.events or 100000, "epochs": a.epochs,
-                "final_train_mse": hist[-1], "labels": "certified BnB optimum d_hat"}
-        save(net, a.out, meta)
-        meta["eval"] = evaluate(ctx, net, a.eval_windows, n_events=a.events or None, log=log)
-        save(net, a.out, meta)
+        meta = {"config": a.config, "generator": SETUPS[a.config][0], "first_window": SETUPS[a.config][1],
+                "windows": int(a.windows), "events": a.events or "generator", "epochs": a.epochs,
+                "final_train_mse": hist[-1], "labels": "certified BnB optimum d_hat",
+                "label_mean": float(labels.mean())}
+        out = a.out or path
+        save(net, out, meta)
+        meta["eval"] = evaluate(ctx, net, a.eval_windows, n_events=a.events or None, log=log, setup=a.config,
+                                label_mean=float(labels.mean()))
+        save(net, out, meta)
     else:
-        net, meta = load(ctx, a.weights)
-        evaluate(ctx, net, a.eval_windows, n_events=a.events or None, log=log)
+        net, meta = load(ctx, a.weights or path)
+        evaluate(ctx, net, a.eval_windows, n_events=a.events or None, log=log, setup=a.config,
+                 label_mean=float(meta.get("label_mean", 0.425)))
 
 
 if __name__ == "__main__":

@@ -219,3 +219,45 @@ def test_trained_network_gains_on_held_out_windows(ctx):
     print(f"forward {t_fwd * 1e3:.3f} ms for {len(wins)} images, seeded search {t_search * 1e3:.2f} ms")
     assert t_fwd < 0.02 * t_search
     net.close()
+
+
+def test_trained_1280x720_network_gains_on_the_benchmark_windows(ctx):
+    """The committed network of the 1280x720 sensor (trained on windows from
+    index 100000 on) on the benchmark's first 64 windows: its error against
+    the certified optimum beats a constant guess; the optimum is the same
+    with and without its seeds; the seeds save node expansions in the
+    canonical search and with the gamma stop of Sec. 6."""
+    import os
+
+    import torch
+
+    from paper_2209_13168_amd import ecmd, learned
+    from paper_2209_13168_amd.learned import windows_chunks
+
+    path = os.path.join(os.path.dirname(learned.__file__), "weights", "cnn_c5.npz")
+    assert os.path.exists(path), "trained weights are missing"
+    net, meta = learned.load(ctx, path)
+    assert meta["config"] == "c5" and meta["first_window"] >= 1000
+    x, y, t, off, tau, _ = next(windows_chunks(list(range(64)), cfg="c5", chunk=64))
+    dev = torch.device("cuda:0")
+    x, y, t, off, tau = (torch.from_numpy(a).to(dev) for a in (x, y, t, off, tau))
+    _, _, _, sensor, search = learned.SETUPS["c5"]
+    sen = ecmd.sensor(*sensor)
+    plain = ctx.estimate_batched(sen, x, y, t, off, tau, **search)
+    seeded = ctx.estimate_learned(net, sen, x, y, t, off, tau, **search)
+    assert [(r.j_star, r.K) for r in plain] == [(r.j_star, r.K) for r in seeded]
+    pred = net.forward(ctx.downsample(sen, x, y, off)).cpu().numpy()
+    lab = np.array([r.d_hat for r in plain])
+    err = np.abs(pred - lab).mean()
+    const = np.abs(np.median(lab) - lab).mean()
+    n_plain = sum(r.nodes_expanded for r in plain)
+    n_seed = sum(r.nodes_expanded for r in seeded)
+    g_plain = ctx.estimate_batched(sen, x, y, t, off, tau, **search, gamma=0.025)
+    g_seed = ctx.estimate_learned(net, sen, x, y, t, off, tau, **search, gamma=0.025)
+    ng_plain = sum(r.nodes_expanded for r in g_plain)
+    ng_seed = sum(r.nodes_expanded for r in g_seed)
+    print(f"network |d - d_hat| {err:.4f} (constant guess {const:.4f}); nodes {n_plain} without seeds, "
+          f"{n_seed} with; gamma 0.025: {ng_plain} and {ng_seed}")
+    assert err < 0.5 * const
+    assert n_seed < n_plain and ng_seed < ng_plain
+    net.close()
