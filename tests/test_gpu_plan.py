@@ -87,6 +87,25 @@ def test_plan_equals_the_synchronous_call_and_the_oracle(ctx, orc):
     plan.close()
 
 
+def test_plan_gamma_stop_equals_the_synchronous_call(ctx, orc):
+    """Algorithm 1's gamma stop (Sec. 6) with certified children in the plan:
+    the synchronous call's results field for field, each within gamma of
+    the oracle's optimum with a gap that covers the loss."""
+    wins = config_windows("c2", range(4), n_events=30_000)
+    s = wins[0].spec
+    x, y, t, off, tau = pack_batch(wins)
+    M2 = float(s.width * s.height) ** 2
+    sync = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, gamma=0.025)
+    plan = ctx.batch_plan(_sensor(s), s.d_lo, s.d_hi, s.eps, max_windows=4, max_events=int(off[-1]), gamma=0.025)
+    got = _launch(plan, *_dev(x, y, t, off, tau))
+    for i, w in enumerate(wins):
+        _same(got[i], sync[i])
+        o = orc.bnb(orc.Events.of_window(w), s.d_lo, s.d_hi, s.eps)
+        lost = (o.K - got[i].K) / M2
+        assert got[i].status == 0 and 0.0 <= lost <= got[i].gap <= 0.025, (i, got[i], o)
+    plan.close()
+
+
 def test_plan_on_guest_tiles_with_rebinning(ctx):
     """640x480 windows: quadrants split into tiles, guest copies, the four
     re-binnings of the launch."""
