@@ -96,6 +96,27 @@ def test_bnb_batched_matches_oracle(ctx, orc):
         _same(r, orc.bnb_pol(_pol_events(orc, w), s1.d_lo, s1.d_hi, s1.eps))
 
 
+def test_gamma_stop_with_certificates(ctx, orc):
+    """Algorithm 1's gamma stop (Sec. 6) on the polarity-aware contrast, with
+    certified children: each result within gamma of the oracle's polarity
+    optimum, its gap covering the loss, its key the oracle's at the returned
+    point."""
+    ws = config_windows("c2", range(4), n_events=30_000)
+    s = ws[0].spec
+    x, y, t, off, tau = pack_batch(ws)
+    p = np.concatenate([w.p for w in ws])
+    M2 = (2.0 * s.width * s.height) ** 2
+    res = ctx.estimate_batched(_sensor(s), x, y, t, off, tau, s.d_lo, s.d_hi, s.eps, polarity=p, gamma=0.025)
+    assert sum(r.bound_certs for r in res) > 0
+    for w, r in zip(ws, res):
+        ev = _pol_events(orc, w)
+        o = orc.bnb_pol(ev, s.d_lo, s.d_hi, s.eps)
+        lost = (o.K - r.K) / M2
+        assert r.status == 0 and 0.0 <= lost <= r.gap <= 0.025, (r, o)
+        S, N = orc.point_pol(ev, r.d_hat)
+        assert orc.key(2 * s.width * s.height, S, N) == r.K
+
+
 @pytest.mark.parametrize("k", range(6))
 def test_bnb_tiny_windows(ctx, orc, k):
     w = config_windows("tiny", [k])[0]
