@@ -260,4 +260,7 @@ def test_trained_1280x720_network_gains_on_the_benchmark_windows(ctx):
           f"{n_seed} with; gamma 0.025: {ng_plain} and {ng_seed}")
     assert err < 0.5 * const
     assert n_seed < n_plain and ng_seed < ng_plain
+    M2 = float(sensor[0] * sensor[1]) ** 2
+    for r, q in zip(g_seed, plain):  # gamma-optimal, with a gap that covers the loss
+        assert 0.0 <= (q.K - r.K) / M2 <= r.gap + 1e-12 and r.gap <= 0.025
     net.close()
