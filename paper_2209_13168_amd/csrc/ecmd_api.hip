@@ -677,7 +677,8 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
         const double tau = (double)c->h_tau[w];
         r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * tau);
         // no finite gap certified: a frontier overflow, or a search cut
-        // short while a node kept on its endpoint certificate was queued
+        // short while a node kept on its endpoint certificate, with no
+        // exactly bounded ancestor, was queued
         if (s.status == ECMD_EFRONTIER || s.gap_hi < 0) r.gap = INFINITY;
         else r.gap = key_to_double(s.gap_hi, s.gap_lo) / M2;
         r.n_events = c->h_off[w + 1] - c->h_off[w];

@@ -1647,7 +1647,8 @@ __global__ void k_plan_results(Search sp, int B, const WinState* __restrict__ st
     const double t = (double)tau[w];
     r.d_end = (double)r.d_hat / (1.0 - (double)r.d_hat * t);
     // no finite gap certified: a frontier overflow, or a search cut short
-    // while a node kept on its endpoint certificate was queued
+    // while a node kept on its endpoint certificate, with no exactly bounded
+    // ancestor, was queued
     r.gap = (s.status == -5 || s.gap_hi < 0) ? (double)INFINITY : i128_to_double(mk128(s.gap_hi, s.gap_lo)) / M2;
     r.n_events = off[w + 1] - off[w];
     r.nodes_expanded = s.nodes_expanded;
