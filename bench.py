@@ -71,11 +71,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "7f0d95524d2b561bd5bee82dea02b56532fa7be6d2ed5e75bb9ac8282e5bec7d",
+    "sources_sha256": "b3dfc3cc103c93a768f407d23df6f497b3e400cc4e7723acbbcb7d8e036aac2b",
     "workload": {"config": "c5", "windows": 256, "frontier_batch": 96},
-    "fetch_kib": 5805669.9,
-    "write_kib": 7119.1,
-    "fetch_bytes_per_kib": 1073741824 / 524304.6,
+    "fetch_kib": 5792770.3,
+    "write_kib": 7121.8,
+    "fetch_bytes_per_kib": 1073741824 / 524305.0,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
