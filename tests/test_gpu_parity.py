@@ -217,12 +217,19 @@ def test_edge_cases(ctx, orc):
         (np.full(7, 30.0, np.float32), np.full(7, 40.0, np.float32), np.full(7, 0.5, np.float32)),
         (np.full(5, 64.0, np.float32), np.full(5, 64.0, np.float32), np.linspace(0, 0.5, 5).astype(np.float32)),
     ]
+    M2 = float(W * H) ** 2
     for x, y, t in cases:
         ev = orc.Events(x, y, t, 0.5, W, H, spec.foe)
         o = orc.bnb(ev, 0.0, 1.0, 1e-3)
         r = ctx.estimate_batched(_sensor(spec), x, y, t, np.array([0, x.size], np.int64),
                                  np.array([0.5], np.float32), 0.0, 1.0, 1e-3)[0]
         _check_same(r, o)
+        # the gamma stop (with certified children): gamma-optimal, the gap covering the loss
+        g = ctx.estimate_batched(_sensor(spec), x, y, t, np.array([0, x.size], np.int64),
+                                 np.array([0.5], np.float32), 0.0, 1.0, 1e-3, gamma=0.025)[0]
+        assert g.status == 0 and 0.0 <= (o.K - g.K) / M2 <= g.gap <= 0.025, (g, o)
+        S, N = orc.point(ev, g.d_hat)
+        assert orc.key(ev.M, S, N) == g.K
 
 
 def test_invalid_arguments_rejected(ctx):
