@@ -385,14 +385,12 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
 // compares where the ray meets the next vertical and horizontal pixel
 // edges; within 2^-8 px of the corner both side pixels are counted.
 // Increments do not return the old count, so no step waits on the LDS;
-// the item's sum of squares comes from one pass over the tile afterwards.
+// the item's sum of squares and its count of increments come from one pass
+// over the tile afterwards (no walk counts its own steps).
 // The corner test computes X - x as kx - (x - 1) or kx - x (the edge ahead
 // is kx + 1 or kx), the same fp64 value as X - x, so decisions do not change.
 // Pixels outside the tile are clamped onto its one-cell border (`Ring`),
 // whose counts are removed at the end.
-struct WalkAcc {
-    unsigned visits;  // walk increments (the start pixels are counted by the caller)
-};
 
 // The tile's counters in LDS with a one-cell border: pixel (kx, ky), clamped
 // to [xlo, xhi] x [ylo, yhi] = [x0 - 1, x0 + tw] x [y0 - 1, y0 + th], is
@@ -443,7 +441,7 @@ __device__ __forceinline__ void tile_add(unsigned* org, const Ring& R, int px, i
 }
 
 __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, int ky, int kxb,
-                                          int kyb, float xf, float yf, float axf, float ayf, WalkAcc& acc) {
+                                          int kyb, float xf, float yf, float axf, float ayf) {
     // a single step along a row or a column (|dx| + |dy| = 1, i.e.
     // dx^2 + dy^2 = 1) has no corner to test: it visits the end pixel only
     // (the coordinates are clamped to [-1, W] x [-1, H], so the squares are
@@ -451,7 +449,6 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
     {
         const int dx = kxb - kx, dy = kyb - ky;
         if (__mul24(dx, dx) + __mul24(dy, dy) == 1) {
-            acc.visits += 1u;
             tile_add(org, R, kxb, kyb);
             return;
         }
@@ -459,10 +456,6 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
     // step direction of each coordinate (not used once it is at its end)
     const bool px = kxb > kx, py = kyb > ky;
     const int sx = px ? 1 : -1, sy = py ? 1 : -1;
-    // increments: one per unit step of either coordinate, and one more for
-    // each corner that counts both side pixels (that step moves both
-    // coordinates and adds three)
-    acc.visits += (unsigned)(abs(kxb - kx) + abs(kyb - ky));
     if (kx != kxb && ky != kyb) {
         // the edges ahead are X = kx + px and Y = ky + py; with the origin
         // moved to (x - px, y - py) (exact in fp64), X - x = kx - xo exactly
@@ -478,7 +471,6 @@ __device__ __forceinline__ void walk_tile(unsigned* org, const Ring& R, int kx, 
             if (!lo && !hi) {  // the ray passes near the corner: both side pixels
                 tile_add(org, R, kx + sx, ky);
                 tile_add(org, R, kx, ky + sy);
-                acc.visits += 1;
             }
             kx += !hi ? sx : 0;
             ky += !lo ? sy : 0;
@@ -601,13 +593,11 @@ __global__ __launch_bounds__(NT) void k_eval(
         const Hyp hp = hyps[wh];
 
         unsigned long long nlow = 0;
-        unsigned visits = 0;  // increments by this thread: one per event, plus walk steps
         // the segment's events, indexed from its start with 32-bit offsets
         // (byte offsets fit 32 bits: a segment holds fewer than 2^28 events)
         const char* __restrict__ sev = reinterpret_cast<const char*>(ev + beg);
         const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
         const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
-        visits = (unsigned)tid < nseg ? (nseg - 1u - (unsigned)tid) / NT + 1u : 0u;
         unsigned long long ucert = 0;  // certificate: walk pixels of the events inside at both ends
         if (hp.kind == HYP_CERT) {
             // Endpoint certificate of an interval (eqs. (17)-(20) without
@@ -615,7 +605,6 @@ __global__ __launch_bounds__(NT) void k_eval(
             // event with both endpoint pixels in the image walks through
             // |dkx| + |dky| + 1 distinct image pixels at least.
             const float ra = hp.ra, rb = hp.rb;
-            visits = 0;
             unsigned nl = 0;
             const auto one = [&](const float4& e) {
                 const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
@@ -667,7 +656,6 @@ __global__ __launch_bounds__(NT) void k_eval(
         } else {
             // Interval hypothesis (eqs. (17)-(20)): endpoints, N_low, walk.
             const float ra = hp.ra, rb = hp.rb;
-            WalkAcc acc{0u};
             unsigned nlow32 = 0;
             const auto one = [&](const float4& e, unsigned i) {
                 const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
@@ -678,25 +666,22 @@ __global__ __launch_bounds__(NT) void k_eval(
                 nlow32 += (unsigned)(i < nown) & (unsigned)(umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
                           (unsigned)(umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
                 tile_add(org, R, kxa, kya);
-                if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
+                if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
             };
             // Owned events first (N_low counts them), then the guest copies:
             // a guest whose walk box for this interval misses the tile would
-            // only increment the discarded border, so it is skipped (and its
-            // increments are not counted).  Two events in flight ahead of the
-            // one being binned (the loads may read up to two strides past a
-            // range: the store is padded by kEvalPad records).
-            unsigned skipped = 0;
+            // only increment the discarded border, so it is skipped.  Two
+            // events in flight ahead of the one being binned (the loads may
+            // read up to two strides past a range: the store is padded by
+            // kEvalPad records).
             const int gx1 = x0 + tw - 1, gy1 = y0 + th - 1;
             const auto guest = [&](const float4& e, unsigned i) {
                 const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
                 const int kxb = flr_clamp(fmaf(e.z, rb, e.x), g.W), kyb = flr_clamp(fmaf(e.w, rb, e.y), g.H);
                 const bool miss = max(kxa, kxb) < x0 || min(kxa, kxb) > gx1 || max(kya, kyb) < y0 || min(kya, kyb) > gy1;
-                if (miss) {
-                    skipped += 1;
-                } else {
+                if (!miss) {
                     tile_add(org, R, kxa, kya);
-                    if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w, acc);
+                    if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
                 }
             };
             const auto run = [&](unsigned i, unsigned lim, auto&& f) {
@@ -720,22 +705,21 @@ __global__ __launch_bounds__(NT) void k_eval(
             };
             run((unsigned)tid, nown, one);
             run(nown + (unsigned)tid, nseg, guest);
-            // start pixels: this thread's owned events and guests, less the skipped guests
-            visits = ((unsigned)tid < nown ? (nown - 1u - (unsigned)tid) / NT + 1u : 0u) +
-                     (nown + (unsigned)tid < nseg ? (nseg - 1u - nown - (unsigned)tid) / NT + 1u : 0u) - skipped;
-            visits += acc.visits;
             nlow = nlow32;
         }
-        // The border counters' squares and counts are removed, then the sum
-        // of squares is taken over the whole counter region, 16 bytes per
-        // read, and the region is zeroed for the next hypothesis (every
-        // counter is zero between hypotheses).  Each thread takes some
-        // counters (its own sums may wrap; the workgroup's totals are exact).
+        // The border counters' squares and counts are removed, then the sums
+        // of the counters and of their squares are taken over the whole
+        // counter region, 16 bytes per read, and the region is zeroed for the
+        // next hypothesis (every counter is zero between hypotheses).  The
+        // sum of the counters less the border's is the hypothesis's count of
+        // in-tile increments (every increment lands in one counter).  Each
+        // thread takes some counters (its own sums may wrap; the workgroup's
+        // totals are exact).
         // (A certificate touched no counter: it skips both passes, not the
         // barrier, which also orders thread 0's reads of the reduction
         // scratch before the next writes.)
         __syncthreads();
-        unsigned long long sq = ucert, hits = visits;
+        unsigned long long sq = ucert, hits = 0;
         if (hp.kind != HYP_CERT) {
             for (int k = tid; k < nring; k += NT) {
                 int idx;
@@ -762,6 +746,7 @@ __global__ __launch_bounds__(NT) void k_eval(
                 t4[i] = make_uint4(0u, 0u, 0u, 0u);
                 sq += (unsigned long long)v.x * v.x + (unsigned long long)v.y * v.y +
                       (unsigned long long)v.z * v.z + (unsigned long long)v.w * v.w;
+                hits += (unsigned long long)v.x + v.y + v.z + v.w;
             }
         }
         // block reduction of (S, hits, nlow)
