@@ -71,10 +71,10 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "b3dfc3cc103c93a768f407d23df6f497b3e400cc4e7723acbbcb7d8e036aac2b",
+    "sources_sha256": "97833e6c3f01d1b11edf095eecaef00020fdf44737d0f90f15ddb24948b9a353",
     "workload": {"config": "c5", "windows": 256, "frontier_batch": 96},
-    "fetch_kib": 5792770.3,
-    "write_kib": 7121.8,
+    "fetch_kib": 5764870.9,
+    "write_kib": 7123.9,
     "fetch_bytes_per_kib": 1073741824 / 524305.0,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
