@@ -670,16 +670,21 @@ __global__ __launch_bounds__(NT) void k_eval(
             };
             // Owned events first (N_low counts them), then the guest copies:
             // a guest whose walk box for this interval misses the tile would
-            // only increment the discarded border, so it is skipped.  Two
-            // events in flight ahead of the one being binned (the loads may
-            // read up to two strides past a range: the store is padded by
+            // only increment the discarded border, so it is skipped, tested
+            // on the warped coordinates before their floor (for an integer
+            // edge e, floor(v) < e exactly when v < e, and the clamp to the
+            // image cannot move a coordinate across an edge of the tile).
+            // Two events in flight ahead of the one being binned (the loads
+            // may read up to two strides past a range: the store is padded by
             // kEvalPad records).
-            const int gx1 = x0 + tw - 1, gy1 = y0 + th - 1;
+            const float fx0 = (float)x0, fx1 = (float)(x0 + tw), fy0 = (float)y0, fy1 = (float)(y0 + th);
             const auto guest = [&](const float4& e, unsigned i) {
-                const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
-                const int kxb = flr_clamp(fmaf(e.z, rb, e.x), g.W), kyb = flr_clamp(fmaf(e.w, rb, e.y), g.H);
-                const bool miss = max(kxa, kxb) < x0 || min(kxa, kxb) > gx1 || max(kya, kyb) < y0 || min(kya, kyb) > gy1;
+                const float xa = fmaf(e.z, ra, e.x), ya = fmaf(e.w, ra, e.y);
+                const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
+                const bool miss = fmaxf(xa, xb) < fx0 || fminf(xa, xb) >= fx1 || fmaxf(ya, yb) < fy0 || fminf(ya, yb) >= fy1;
                 if (!miss) {
+                    const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
+                    const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
                     tile_add(org, R, kxa, kya);
                     if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
                 }
