@@ -609,8 +609,8 @@ __global__ __launch_bounds__(NT) void k_eval(
             const auto one = [&](const float4& e) {
                 const int kxa = flr_clamp(fmaf(e.z, ra, e.x), g.W), kya = flr_clamp(fmaf(e.w, ra, e.y), g.H);
                 const int kxb = flr_clamp(fmaf(e.z, rb, e.x), g.W), kyb = flr_clamp(fmaf(e.w, rb, e.y), g.H);
-                const bool full = (umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
-                                  (umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
+                // both endpoints in the image, i.e. the far one (see the interval path)
+                const bool full = ((unsigned)kxb < (unsigned)g.W) & ((unsigned)kyb < (unsigned)g.H);
                 nl += full ? 1u : 0u;
                 ucert += full ? (unsigned)(abs(kxb - kxa) + abs(kyb - kya) + 1) : 0u;
             };
@@ -662,9 +662,12 @@ __global__ __launch_bounds__(NT) void k_eval(
                 const float xb = fmaf(e.z, rb, e.x), yb = fmaf(e.w, rb, e.y);
                 const int kxa = flr_clamp(xa, g.W), kya = flr_clamp(ya, g.H);
                 const int kxb = flr_clamp(xb, g.W), kyb = flr_clamp(yb, g.H);
-                // both endpoints in the image: neither clamped to -1 (as unsigned, huge) nor to W, H
-                nlow32 += (unsigned)(i < nown) & (unsigned)(umax((unsigned)kxa, (unsigned)kxb) < (unsigned)g.W) &
-                          (unsigned)(umax((unsigned)kya, (unsigned)kyb) < (unsigned)g.H);
+                // both endpoints in the image, i.e. the far one (not clamped to
+                // -1, huge as unsigned, nor to W, H): the warp only moves an
+                // event away from the FOE as the rate grows, so an event inside
+                // at rb is inside at ra <= rb
+                nlow32 += (unsigned)(i < nown) & (unsigned)((unsigned)kxb < (unsigned)g.W) &
+                          (unsigned)((unsigned)kyb < (unsigned)g.H);
                 tile_add(org, R, kxa, kya);
                 if (kxa != kxb || kya != kyb) walk_tile(org, R, kxa, kya, kxb, kyb, e.x, e.y, e.z, e.w);
             };

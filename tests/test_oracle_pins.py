@@ -190,6 +190,30 @@ def test_bound_equals_point_at_singletons(orc):
         assert (Sb, Nl) == (S, N) and np.array_equal(Hb, Hp)
 
 
+@pytest.mark.parametrize("cfg,n,foe", [("c2", 30_000, None), ("c3", 20_000, None), ("c5", 20_000, None),
+                                       ("c2", 20_000, (101.3, 57.85)), ("c1", 10_000, None)])
+def test_n_low_is_the_in_image_count_at_the_far_end(orc, cfg, n, foe):
+    """Eq. (12) moves every event away from the FOE as d grows (the warped
+    coordinate is a monotone fp32 function of the rate, which grows with d),
+    so an event inside the image at the far end of an interval is inside at
+    the near end too: N_low of [d_a, d_b] (events inside at both ends) equals
+    N of the point d_b.  Random intervals of every depth, and the range's
+    ends."""
+    w = config_windows(cfg, [3], n_events=n)[0]
+    s = w.spec
+    ev = orc.Events(w.x, w.y, w.t_rel, s.tau, s.width, s.height, foe or s.foe)
+    rng = np.random.default_rng(17)
+    L = orc.depth(s.d_lo, s.d_hi, s.eps)
+    for depth in sorted({0, 1, 2, 4, 7, 11, 15, L - 1} & set(range(L))):
+        size = 1 << (L - depth)
+        for _ in range(3):
+            ja = int(rng.integers(0, 1 << depth)) * size
+            d_a, d_b = orc.grid_d(s.d_lo, s.d_hi, L, ja), orc.grid_d(s.d_lo, s.d_hi, L, ja + size)
+            _, n_low = orc.bound(ev, d_a, d_b)
+            _, n_b = orc.point(ev, d_b)
+            assert n_low == n_b, (cfg, depth, d_a, d_b)
+
+
 def test_bound_valid_near_pixel_corners(orc):
     """Eq. (18) where fp32 rounding matters most: rays that pass within about
     an ulp of a pixel corner, probed at every fp32 d near the crossing.  The
