@@ -359,7 +359,7 @@ static int run_prep(ecmd_ctx* c, const Geometry& g, const Inputs& in, int B, flo
     const size_t nctr = prep_counters(B, T);
     HIPCHK(c, c->cnt_own.ensure(sizeof(int) * nctr));
     HIPCHK(c, c->seg_off.ensure(sizeof(long long) * (B * T + 1)));
-    HIPCHK(c, c->seg_own.ensure(sizeof(int) * B * T));
+    HIPCHK(c, c->seg_own.ensure(sizeof(int) * seg_own_words(B, T)));
     HIPCHK(c, c->cursor.ensure(sizeof(unsigned long long) * nctr));
     HIPCHK(c, c->err_flag.ensure(sizeof(int) * B));
     HIPCHK(c, hipMemsetAsync(c->cnt_own.p, 0, sizeof(int) * nctr, c->stream));
@@ -558,7 +558,7 @@ static int run_search(ecmd_ctx* c, const ecmd_sensor* sensor, const Inputs& in, 
             hipEvent_t a = nullptr, b = nullptr;
             if (timed) tm.pair(0, a, b);
             hipError_t e = launch_eval(c->stream, g, nb, nt, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                                       c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(),
+                                       c->seg_own.as<int>(), c->wp.as<WinParam>(), c->hyps.as<Hyp>(), c->act.as<int>(),
                                        c->items.as<Item>(), qcap, &q[parity * kXcd], &q[(1 - parity) * kXcd],
                                        c->part.as<Part>(), sp.HS, nullptr, a, b);
             if (e != hipSuccess) return e;
@@ -790,7 +790,7 @@ static void plan_sizes(const PlanShape& sh, size_t* bytes) {
     bytes[PB_BLK] = sizeof(int) * (Bm + 1);
     bytes[PB_CNT] = sizeof(int) * nctr;
     bytes[PB_SEG_OFF] = sizeof(long long) * ((size_t)Bm * T + 1);
-    bytes[PB_SEG_OWN] = sizeof(int) * (size_t)Bm * T;
+    bytes[PB_SEG_OWN] = sizeof(int) * seg_own_words(Bm, T);
     bytes[PB_CURSOR] = sizeof(unsigned long long) * nctr;
     bytes[PB_EV] = sizeof(float4) * (size_t)(sh.lim.max_records + kEvalPad);  // padded as in the synchronous call
     bytes[PB_WERR] = sizeof(int) * Bm;
@@ -933,7 +933,7 @@ static int plan_enqueue(ecmd_ctx* c, const PlanShape& sh, void* const* b, const 
         for (int k = 0; k < 8; ++k) {  // four steps of two phases
             const int parity = k & 1;
             HIPCHK(c, launch_eval(s, g, sh.nb, sh.nt, sh.lds, (const float4*)b[PB_EV], seg_off,
-                                  (const int*)b[PB_SEG_OWN], hyps, act, items, sh.qcap, &q[parity * kXcd],
+                                  (const int*)b[PB_SEG_OWN], wp, hyps, act, items, sh.qcap, &q[parity * kXcd],
                                   &q[(1 - parity) * kXcd], part, sp.HS, nullptr));
             HIPCHK(c, launch_frontier(s, parity, sp, wp, B, T, seg_off, st, (Node*)b[PB_FRONT], sel, hyps, act, part,
                                       items, sh.qcap, &q[(1 - parity) * kXcd], (int*)b[PB_NACTIVE]));
@@ -1537,8 +1537,8 @@ static int probe_impl(ecmd_ctx* c, const ecmd_sensor* sensor, const float* x, co
     HIPCHK(c, eval_setup(c, lds, nt, &nb));
     Queue* q = c->queues.as<Queue>();
     HIPCHK(c, launch_eval(c->stream, g, nb, nt, lds, c->ev.as<float4>(), c->seg_off.as<long long>(),
-                          c->seg_own.as<int>(), c->hyps.as<Hyp>(), c->act.as<int>(), c->items.as<Item>(),
-                          (int)items.size(), &q[0], &q[kXcd], c->part.as<Part>(), m, dimg));
+                          c->seg_own.as<int>(), c->wp.as<WinParam>(), c->hyps.as<Hyp>(), c->act.as<int>(),
+                          c->items.as<Item>(), (int)items.size(), &q[0], &q[kXcd], c->part.as<Part>(), m, dimg));
     std::vector<Part> parts(items.size());
     std::vector<long long> seg(T + 1);
     HIPCHK(c, hipMemcpyAsync(parts.data(), c->part.p, sizeof(Part) * parts.size(), hipMemcpyDeviceToHost,

@@ -81,10 +81,17 @@ struct Geometry {
     int ring_px;                  // largest tile's counters with their one-cell border, (w + 2)(h + 2)
 };
 
+// Guest copies of a tile segment are split into kGuestBins bins by the
+// first of the rates gcut[0] <= ... <= gcut[kGuestBins - 2] at which the
+// event has reached the tile (bin m: not reached at gcut[0 .. m-1]), so an
+// evaluation at rates up to r reads the bins whose lower cut lies below r.
+constexpr int kGuestBins = 8;
+
 struct WinParam {
     float tau;
     float r_lo, r_hi;  // rates at d_lo and d_hi
     float kscale;      // walk-length classes per unit of |ax| + |ay|
+    float gcut[kGuestBins - 1];  // guest bin cuts, uniform over [r_lo, r_hi]
     long long n_events;
 };
 
@@ -155,8 +162,12 @@ struct Queue {
 
 hipError_t launch_winparam(hipStream_t s, const Geometry& g, const float* tau, const long long* offsets,
                            int B, float d_lo, float d_hi, WinParam* wp);
-// Counters of the prep (per window, tile, owned/guest and walk class).
+// Counters of the prep (per window and tile: owned events by walk class,
+// guests by bin and walk class).
 size_t prep_counters(int B, int T);
+// Ints of seg_own: per window and tile, the owned events, then the end of
+// each guest bin, counted from the segment's start.
+size_t seg_own_words(int B, int T);
 // phase 0: count events per (window, tile, owned/guest, walk class) and scan
 // into segments; err_flag[w] is set when window w has an invalid event.
 // phase 1: scatter the events into their segments; with cap >= 0, seg_off
@@ -191,7 +202,7 @@ hipError_t launch_frontier(hipStream_t s, int phase, const Search& sp, const Win
                            hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // q, q_reset: kXcd queues each; nt: threads per workgroup (256, 512 or 1024)
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes,
-                       const float4* ev, const long long* seg_off, const int* seg_own,
+                       const float4* ev, const long long* seg_off, const int* seg_own, const WinParam* wp,
                        const Hyp* hyps, const int* act, const Item* items, int qcap, Queue* q, Queue* q_reset,
                        Part* part, int HS, unsigned* img_out, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 hipError_t launch_rates(hipStream_t s, const float* d_a, const float* d_b, int m, float tau, Hyp* hyps);

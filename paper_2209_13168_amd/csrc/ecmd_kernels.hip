@@ -141,6 +141,23 @@ __device__ __forceinline__ unsigned long long wave_total(unsigned long long v) {
 // is about (|ax| + |ay|)(r_b - r_a) pixels long, so neighbouring lanes of a
 // wave then walk similar distances.
 constexpr int kNB = 16;
+// Guests keep half as many walk classes (kNB / 2 per guest bin).
+constexpr int kNG = kNB / 2;
+// Prep counters of one tile segment: owned by walk class, then guests by
+// bin and walk class, so a segment holds its owned events first and its
+// guest bins in increasing order.
+constexpr int kTC = kNB + kGuestBins * kNG;
+
+// Guest bin cuts of a window, uniform over its binning range [r_lo, r_hi]
+// and non-decreasing whatever the rounding.
+__device__ __forceinline__ void set_guest_cuts(WinParam& p) {
+    const float span = p.r_hi - p.r_lo;
+    float prev = p.r_lo;
+    for (int m = 1; m < kGuestBins; ++m) {
+        prev = fmaxf(prev, fmaf((float)m * (1.0f / kGuestBins), span, p.r_lo));
+        p.gcut[m - 1] = prev;
+    }
+}
 
 __global__ void k_winparam(const float* __restrict__ tau, const long long* __restrict__ offsets, int B,
                            float d_lo, float d_hi, int W, int H, float cx, float cy, WinParam* __restrict__ wp) {
@@ -153,6 +170,7 @@ __global__ void k_winparam(const float* __restrict__ tau, const long long* __res
     const float key_max = (fmaxf(fabsf(cx), fabsf((float)W - cx)) + fmaxf(fabsf(cy), fabsf((float)H - cy))) * p.tau;
     p.kscale = key_max > 0.0f ? (float)kNB / key_max : 0.0f;
     p.n_events = offsets[w + 1] - offsets[w];
+    set_guest_cuts(p);
     wp[w] = p;
 }
 
@@ -176,8 +194,10 @@ __device__ __forceinline__ int window_of_block(const int* blk_start, int B, int 
 }
 
 __device__ __forceinline__ int band_of(const int* cut, int n, int k) {
+    // the cuts increase: the band is the count of inner cuts at or below k
+    // (every lane runs the same loop, so the cuts are read as scalars)
     int b = 0;
-    while (b + 1 < n && cut[b + 1] <= k) ++b;
+    for (int j = 1; j < n; ++j) b += cut[j] <= k ? 1 : 0;
     return b;
 }
 
@@ -204,8 +224,36 @@ __device__ __forceinline__ int walk_class(float ax, float ay, float kscale) {
     return kNB - 1 - min(max(b, 0), kNB - 1);
 }
 
-// counter of (tile, owned 0 / guest 1, walk class) inside a window
-__device__ __forceinline__ int ctr_of(int t, int og, int b) { return (t * 2 + og) * kNB + b; }
+// counters of an owned event and of a guest copy in bin m, inside a window
+__device__ __forceinline__ int ctr_own(int t, int b) { return t * kTC + b; }
+__device__ __forceinline__ int ctr_guest(int t, int m, int b) { return t * kTC + kNB + m * kNG + (b >> 1); }
+
+// Cuts at which one coordinate of an event, warped by the evaluation's own
+// fmaf (v + a r), is still short of the edge e of a band, e being the edge
+// the coordinate moves towards as the rate grows (the lower one for a >= 0).
+// The test is monotone in the rate, so the cuts at which it holds come
+// first.  A guest copy's bin is the larger of its two coordinates' counts:
+// the event has not reached the tile while either coordinate is short, and
+// the union of two leading runs of cuts is the longer one.  A bin-m copy
+// evaluated at rates that are all at most gcut[m - 1] lies outside the tile
+// at both ends, on the same side, and adds only to the tile's border.
+__device__ __forceinline__ int cuts_short(const WinParam& p, float v, float a, float e) {
+    const bool neg = a < 0.0f;
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < kGuestBins - 1; ++k) m += ((fmaf(a, p.gcut[k], v) < e) != neg) ? 1 : 0;
+    return m;
+}
+
+// Band edges of the tile grid as floats, in LDS for the prep blocks.
+struct PrepCuts {
+    float col[kMaxTiles + 1], row[kMaxTiles + 1];
+};
+
+__device__ __forceinline__ void load_cuts(const Geometry& g, PrepCuts& c) {
+    for (int k = threadIdx.x; k <= g.ntx; k += blockDim.x) c.col[k] = (float)g.colcut[k];
+    for (int k = threadIdx.x; k <= g.nty; k += blockDim.x) c.row[k] = (float)g.rowcut[k];
+}
 
 // First segment of event i's image: the polarity-aware contrast keeps one
 // event image per polarity (p > 0: the second), each tiled alike.
@@ -214,7 +262,26 @@ __device__ __forceinline__ int seg_base(const Geometry& g, const signed char* po
 }
 
 constexpr int kPrepThreads = 256;
-constexpr int kCtr = kMaxTiles * 2 * kNB;
+
+// Counter of every copy of a prepared event (segment base sb), in the
+// same order for the counting and the scattering passes.
+template <class F>
+__device__ __forceinline__ void for_each_copy(const Geometry& g, const WinParam& p, const PrepCuts& c, int sb,
+                                              float x, float y, float ax, float ay, int tx0, int tx1, int ty0,
+                                              int ty1, int cls, F&& f) {
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const int by = cuts_short(p, y, ay, c.row[ay < 0.0f ? ty + 1 : ty]);
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            const int t = sb + ty * g.ntx + tx;
+            if (ty == ty0 && tx == tx0) {
+                f(ctr_own(t, cls));
+            } else {
+                const int bx = cuts_short(p, x, ax, c.col[ax < 0.0f ? tx + 1 : tx]);
+                f(ctr_guest(t, max(bx, by), cls));
+            }
+        }
+    }
+}
 
 // Per-event prep: validity, (ax, ay), reachable tiles and walk class.
 struct PrepEv {
@@ -242,10 +309,12 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
     Geometry g, const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ t_rel,
     const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, int* __restrict__ cnt, int* __restrict__ err_flag) {
-    __shared__ int s_cnt[kCtr];
+    extern __shared__ int s_cnt[];  // g.T * kTC counters
+    __shared__ PrepCuts s_cuts;
     if ((int)blockIdx.x >= blk_start[B]) return;  // a grid sized for the largest batch
-    const int nc = g.T * 2 * kNB;
+    const int nc = g.T * kTC;
     for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
+    load_cuts(g, s_cuts);
     __syncthreads();
     const int w = window_of_block(blk_start, B, blockIdx.x);
     const int c = blockIdx.x - blk_start[w];
@@ -256,51 +325,57 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_count(
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.valid) atomicOr(&err_flag[w], 1);
         if (!e.ok) continue;
-        const int sb = seg_base(g, pol, i);
-        for (int ty = e.ty0; ty <= e.ty1; ++ty)
-            for (int tx = e.tx0; tx <= e.tx1; ++tx)
-                atomicAdd(&s_cnt[ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
+        for_each_copy(g, p, s_cuts, seg_base(g, pol, i), e.x, e.y, e.ax, e.ay, e.tx0, e.tx1, e.ty0, e.ty1, e.cls,
+                      [&](int k) { atomicAdd(&s_cnt[k], 1); });
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nc; k += blockDim.x)
         if (s_cnt[k]) atomicAdd(&cnt[(long long)w * nc + k], s_cnt[k]);
 }
 
-// Exclusive scan of the counters of every (window, tile, owned/guest,
-// class) in that order (one workgroup); then the segment of (w, t) starts
-// at its first counter and its owned events end where its guests begin.
+// Exclusive scan of the counters of every (window, tile, owned/guest bin,
+// class) in that order (one workgroup: a prefix sum inside each wave, the
+// wave totals through LDS, 1024 counters per round); then the segment of
+// (w, t) starts at its first counter, its owned events end where its first
+// guest bin begins, and guest bin m ends where bin m + 1 (or the next
+// segment) begins.
 __global__ __launch_bounds__(1024) void k_prep_scan(int B, int T, const int* __restrict__ cnt,
                                                     long long* __restrict__ seg_off, int* __restrict__ seg_own,
                                                     unsigned long long* __restrict__ cursor) {
-    __shared__ long long s[1024];
-    __shared__ long long carry;
-    const long long n = (long long)B * T * 2 * kNB;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
+    __shared__ long long s_wave[16];
+    __shared__ long long s_carry;
+    const long long n = (long long)B * T * kTC;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_carry = 0;
     for (long long base = 0; base < n; base += 1024) {
         const long long k = base + threadIdx.x;
         const long long v = k < n ? cnt[k] : 0;
-        s[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            long long a = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0;
-            __syncthreads();
-            s[threadIdx.x] += a;
-            __syncthreads();
+        long long incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const long long a = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += a;
         }
-        const long long incl = s[threadIdx.x] + carry;
-        if (k < n) cursor[k] = (unsigned long long)(incl - v);
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = incl;
-        __syncthreads();
+        if (lane == 63) s_wave[wv] = incl;
+        __syncthreads();  // the wave totals and the last round's carry are visible
+        long long pre = s_carry;
+        for (int j = 0; j < wv; ++j) pre += s_wave[j];
+        if (k < n) cursor[k] = (unsigned long long)(pre + incl - v);
+        __syncthreads();  // every read of s_wave and s_carry is done
+        if (threadIdx.x == 1023) s_carry = pre + incl;
     }
+    __syncthreads();  // the total and every cursor are visible
+    const long long total = s_carry;
+    const auto start = [&](long long k) { return k < n ? (long long)cursor[k] : total; };
     for (int st = threadIdx.x; st < B * T; st += 1024) {
-        const long long o0 = (long long)cursor[(long long)st * 2 * kNB];
-        const long long o1 = (long long)cursor[(long long)st * 2 * kNB + kNB];
+        const long long c0 = (long long)st * kTC;
+        const long long o0 = start(c0);
         seg_off[st] = o0;
-        seg_own[st] = (int)(o1 - o0);
+        int* const so = seg_own + (long long)st * (kGuestBins + 1);
+        so[0] = (int)(start(c0 + kNB) - o0);
+        for (int m = 0; m < kGuestBins; ++m) so[1 + m] = (int)(start(c0 + kNB + (m + 1) * kNG) - o0);
     }
-    if (threadIdx.x == 0) seg_off[(long long)B * T] = carry;
+    if (threadIdx.x == 0) seg_off[(long long)B * T] = total;
 }
 
 __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
@@ -308,11 +383,14 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     const signed char* __restrict__ pol, const long long* __restrict__ offsets, const WinParam* __restrict__ wp, int B,
     const int* __restrict__ blk_start, int chunk, unsigned long long* __restrict__ cursor,
     const long long* __restrict__ total, long long cap, float4* __restrict__ ev) {
-    __shared__ int s_cnt[kCtr];
-    __shared__ unsigned long long s_base[kCtr];
+    extern __shared__ unsigned long long s_prep[];  // g.T * kTC bases, then as many counts
+    const int nc = g.T * kTC;
+    unsigned long long* const s_base = s_prep;
+    int* const s_cnt = reinterpret_cast<int*>(s_prep + nc);
+    __shared__ PrepCuts s_cuts;
     if ((int)blockIdx.x >= blk_start[B]) return;
     if (total && *total > cap) return;  // the records would not fit the store: nothing is written
-    const int nc = g.T * 2 * kNB;
+    load_cuts(g, s_cuts);
     for (int k = threadIdx.x; k < nc; k += blockDim.x) s_cnt[k] = 0;
     __syncthreads();
     const int w = window_of_block(blk_start, B, blockIdx.x);
@@ -323,10 +401,8 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
     for (long long i = beg + threadIdx.x; i < end; i += blockDim.x) {
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.ok) continue;
-        const int sb = seg_base(g, pol, i);
-        for (int ty = e.ty0; ty <= e.ty1; ++ty)
-            for (int tx = e.tx0; tx <= e.tx1; ++tx)
-                atomicAdd(&s_cnt[ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls)], 1);
+        for_each_copy(g, p, s_cuts, seg_base(g, pol, i), e.x, e.y, e.ax, e.ay, e.tx0, e.tx1, e.ty0, e.ty1, e.cls,
+                      [&](int k) { atomicAdd(&s_cnt[k], 1); });
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nc; k += blockDim.x) {
@@ -339,17 +415,16 @@ __global__ __launch_bounds__(kPrepThreads) void k_prep_scatter(
         const PrepEv e = prep_event(g, p, x[i], y[i], t_rel[i]);
         if (!e.ok) continue;
         const float4 v = make_float4(e.x, e.y, e.ax, e.ay);
-        const int sb = seg_base(g, pol, i);
-        for (int ty = e.ty0; ty <= e.ty1; ++ty)
-            for (int tx = e.tx0; tx <= e.tx1; ++tx) {
-                const int k = ctr_of(sb + ty * g.ntx + tx, (ty == e.ty0 && tx == e.tx0) ? 0 : 1, e.cls);
-                const int r = atomicAdd(&s_cnt[k], 1);
-                ev[s_base[k] + (unsigned long long)r] = v;
-            }
+        for_each_copy(g, p, s_cuts, seg_base(g, pol, i), e.x, e.y, e.ax, e.ay, e.tx0, e.tx1, e.ty0, e.ty1, e.cls,
+                      [&](int k) {
+                          const int r = atomicAdd(&s_cnt[k], 1);
+                          ev[s_base[k] + (unsigned long long)r] = v;
+                      });
     }
 }
 
-size_t prep_counters(int B, int T) { return (size_t)B * T * 2 * kNB; }
+size_t prep_counters(int B, int T) { return (size_t)B * T * kTC; }
+size_t seg_own_words(int B, int T) { return (size_t)B * T * (kGuestBins + 1); }
 
 hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float* x, const float* y,
                        const float* t_rel, const signed char* pol, const long long* offsets, const WinParam* wp, int B,
@@ -357,8 +432,8 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
                        unsigned long long* cursor, float4* ev, int* err_flag, long long cap) {
     if (phase == 0) {
         if (nblk > 0) {
-            k_prep_count<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cnt,
-                                                       err_flag);
+            k_prep_count<<<nblk, kPrepThreads, sizeof(int) * g.T * kTC, s>>>(g, x, y, t_rel, pol, offsets, wp, B,
+                                                                             blk_start, chunk, cnt, err_flag);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
@@ -366,8 +441,9 @@ hipError_t launch_prep(hipStream_t s, int phase, const Geometry& g, const float*
         return hipGetLastError();
     }
     if (nblk > 0) {
-        k_prep_scatter<<<nblk, kPrepThreads, 0, s>>>(g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cursor,
-                                                     cap >= 0 ? seg_off + (long long)B * g.T : nullptr, cap, ev);
+        k_prep_scatter<<<nblk, kPrepThreads, (sizeof(unsigned long long) + sizeof(int)) * g.T * kTC, s>>>(
+            g, x, y, t_rel, pol, offsets, wp, B, blk_start, chunk, cursor,
+            cap >= 0 ? seg_off + (long long)B * g.T : nullptr, cap, ev);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -516,13 +592,15 @@ size_t eval_lds_bytes(int ring_px) {
 // them for the next hypothesis (the tile region is cleared once, at start).
 // An interval takes the segment's owned events, then its guest copies,
 // skipping a guest whose walk box misses the tile (all its increments would
-// land on the border).  An endpoint certificate reads the owned events only
-// and touches no counter.
+// land on the border).  Points and intervals read the guest bins whose lower
+// cut lies below the hypothesis's larger rate only (the others are short of
+// the tile at every rate it takes).  An endpoint certificate reads the owned
+// events only and touches no counter.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_eval(
     Geometry g, const float4* __restrict__ ev, const long long* __restrict__ seg_off,
-    const int* __restrict__ seg_own, const Hyp* __restrict__ hyps, const int* __restrict__ act,
-    const Item* __restrict__ items, int qcap, Queue* __restrict__ q, Queue* __restrict__ q_reset,
+    const int* __restrict__ seg_own, const WinParam* __restrict__ wp, const Hyp* __restrict__ hyps,
+    const int* __restrict__ act, const Item* __restrict__ items, int qcap, Queue* __restrict__ q, Queue* __restrict__ q_reset,
     Part* __restrict__ part, int HS, unsigned* __restrict__ img_out) {
     constexpr int NW = NT / 64;
     extern __shared__ __align__(16) unsigned smem[];
@@ -586,18 +664,26 @@ __global__ __launch_bounds__(NT) void k_eval(
         const int nring = 2 * R.rw + 2 * th;    // border counters
         const float fxlo = (float)R.xlo, fxhi = (float)R.xhi, fylo = (float)R.ylo, fyhi = (float)R.yhi;
         const long long seg = (long long)w * g.T + t;
-        const long long beg = seg_off[seg], end = seg_off[seg + 1];
-        const long long own_end = beg + seg_own[seg];
+        const long long beg = seg_off[seg];
+        const int* const sown = seg_own + seg * (kGuestBins + 1);
+        const float* const gcut = wp[w].gcut;
       for (int gk = 0; gk < item.cnt; ++gk) {
         const int wh = w * HS + act[w * HS + item.r0 + gk];
         const Hyp hp = hyps[wh];
+        // guest bins read: those whose lower cut lies below the larger rate
+        int nbin = 0;
+        {
+            const float rmax = fmaxf(hp.ra, hp.rb);
+#pragma unroll
+            for (int k = 0; k < kGuestBins - 1; ++k) nbin += gcut[k] < rmax ? 1 : 0;
+        }
 
         unsigned long long nlow = 0;
         // the segment's events, indexed from its start with 32-bit offsets
         // (byte offsets fit 32 bits: a segment holds fewer than 2^28 events)
         const char* __restrict__ sev = reinterpret_cast<const char*>(ev + beg);
         const auto at = [sev](unsigned k) { return *reinterpret_cast<const float4*>(sev + (k << 4)); };
-        const unsigned nseg = (unsigned)(end - beg), nown = (unsigned)(own_end - beg);
+        const unsigned nown = (unsigned)sown[0], nseg = (unsigned)sown[1 + nbin];
         unsigned long long ucert = 0;  // certificate: walk pixels of the events inside at both ends
         if (hp.kind == HYP_CERT) {
             // Endpoint certificate of an interval (eqs. (17)-(20) without
@@ -812,22 +898,23 @@ hipError_t eval_set_lds(size_t bytes) {
 }
 
 hipError_t launch_eval(hipStream_t s, const Geometry& g, int nblocks, int nt, size_t lds_bytes, const float4* ev,
-                       const long long* seg_off, const int* seg_own, const Hyp* hyps, const int* act,
+                       const long long* seg_off, const int* seg_own, const WinParam* wp, const Hyp* hyps,
+                       const int* act,
                        const Item* items, int qcap, Queue* q, Queue* q_reset, Part* part, int HS,
                        unsigned* img_out, hipEvent_t t0, hipEvent_t t1) {
     // the events (nullable) take the kernel's start and end times from its dispatch
     switch (nt) {
         case 256:
             hipExtLaunchKernelGGL(k_eval<256>, dim3(nblocks), dim3(256), (uint32_t)lds_bytes, s, t0, t1, 0u, g, ev,
-                                  seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
+                                  seg_off, seg_own, wp, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
             break;
         case 512:
             hipExtLaunchKernelGGL(k_eval<512>, dim3(nblocks), dim3(512), (uint32_t)lds_bytes, s, t0, t1, 0u, g, ev,
-                                  seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
+                                  seg_off, seg_own, wp, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
             break;
         default:
             hipExtLaunchKernelGGL(k_eval<1024>, dim3(nblocks), dim3(1024), (uint32_t)lds_bytes, s, t0, t1, 0u, g,
-                                  ev, seg_off, seg_own, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
+                                  ev, seg_off, seg_own, wp, hyps, act, items, qcap, q, q_reset, part, HS, img_out);
     }
     return hipGetLastError();
 }
@@ -1511,6 +1598,7 @@ __global__ __launch_bounds__(NTF) void k_live_range(Search sp, const WinState* _
         WinParam p = wp[w];
         p.r_lo = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, s_lo), p.tau);
         p.r_hi = rate_of(grid_d(sp.d_lo, sp.d_hi, sp.L, s_hi), p.tau);
+        set_guest_cuts(p);
         wp[w] = p;
     }
 }
