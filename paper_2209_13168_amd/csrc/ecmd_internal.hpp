@@ -85,7 +85,7 @@ struct Geometry {
 // first of the rates gcut[0] <= ... <= gcut[kGuestBins - 2] at which the
 // event has reached the tile (bin m: not reached at gcut[0 .. m-1]), so an
 // evaluation at rates up to r reads the bins whose lower cut lies below r.
-constexpr int kGuestBins = 8;
+constexpr int kGuestBins = 4;
 
 struct WinParam {
     float tau;

@@ -264,16 +264,21 @@ __device__ __forceinline__ int seg_base(const Geometry& g, const signed char* po
 constexpr int kPrepThreads = 256;
 
 // Counter of every copy of a prepared event (segment base sb), in the
-// same order for the counting and the scattering passes.
+// same order for the counting and the scattering passes.  The event's own
+// copy (the one N_low and the certificates read) goes to the tile it
+// starts in, at the low end of the binning range: the corner of its tile
+// rectangle it moves away from.  Every other tile is a guest, reached at
+// higher rates only.
 template <class F>
 __device__ __forceinline__ void for_each_copy(const Geometry& g, const WinParam& p, const PrepCuts& c, int sb,
                                               float x, float y, float ax, float ay, int tx0, int tx1, int ty0,
                                               int ty1, int cls, F&& f) {
+    const int ox = ax < 0.0f ? tx1 : tx0, oy = ay < 0.0f ? ty1 : ty0;
     for (int ty = ty0; ty <= ty1; ++ty) {
         const int by = cuts_short(p, y, ay, c.row[ay < 0.0f ? ty + 1 : ty]);
         for (int tx = tx0; tx <= tx1; ++tx) {
             const int t = sb + ty * g.ntx + tx;
-            if (ty == ty0 && tx == tx0) {
+            if (ty == oy && tx == ox) {
                 f(ctr_own(t, cls));
             } else {
                 const int bx = cuts_short(p, x, ax, c.col[ax < 0.0f ? tx + 1 : tx]);
