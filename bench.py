@@ -71,11 +71,11 @@ EVENT_RECORD_BYTES = 16
 # --calibrate-copy`).  The figures hold only for the kernel sources and the
 # workload they were taken on; for anything else `traffic` is null.
 TRAFFIC = {
-    "sources_sha256": "f4443c69c87feb5957fa525cfa3a873315b0b00e6e4f488ee64e03f66e09ed68",
+    "sources_sha256": "fdc6d8b0e93706e4a3455bfc52efb26aef555c542fff6116ae86563e543558f0",
     "workload": {"config": "c5", "windows": 256, "frontier_batch": 96},
-    "fetch_kib": 5816282.3,
-    "write_kib": 7113.6,
-    "fetch_bytes_per_kib": 1073741824 / 524304.7,
+    "fetch_kib": 5342178.8,
+    "write_kib": 7266.1,
+    "fetch_bytes_per_kib": 1073741824 / 524304.8,
     "write_bytes_per_kib": 1073741824 / 1048576.0,
 }
 KERNEL_SOURCES = ("paper_2209_13168_amd/csrc/ecmd_kernels.hip", "paper_2209_13168_amd/csrc/ecmd_internal.hpp",
