@@ -156,3 +156,67 @@ def test_images_on_the_1280x720_tiling_with_hot_pixels(ctx, orc):
         So, No, Ho = orc.bound(ev, float(da[k]), float(db[k]), want_image=True)
         assert (int(Sb[k]), int(Nl[k])) == (So, No), (k, da[k], db[k])
         assert np.array_equal(img[k * M:(k + 1) * M], Ho), (k, da[k], db[k])
+
+
+def _rate32(d, tau):
+    """The warp rate of divergence d in fp32, each step rounded as eq. (12)
+    is evaluated on the device: d / (1 - d tau)."""
+    d, tau = np.float32(d), np.float32(tau)
+    return np.float32(d / np.float32(np.float32(1.0) - np.float32(d * tau)))
+
+
+def _ds_around_rate(r, tau, span=24):
+    """fp32 divergences whose rate lies just below, at and just above r."""
+    d0 = np.float32(float(r) / (1.0 + float(r) * float(tau)))
+    bits = np.array([d0], np.float32).view(np.int32)[0]
+    cand = (np.arange(-span, span + 1, dtype=np.int64) + int(bits)).astype(np.int32).view(np.float32)
+    rates = np.array([_rate32(d, tau) for d in cand], np.float32)
+    below = cand[rates < r]
+    at = cand[rates == r]
+    above = cand[rates > r]
+    out = [below[-1], above[0]]
+    if at.size:
+        out.append(at[0])
+    return out
+
+
+def test_bounds_at_the_guest_bin_cuts(ctx, orc):
+    """On the 1280x720 tiling, guest copies of a tile are binned by the rate at
+    which they reach it, at cuts a quarter, a half and three quarters of the
+    way through the binning range's rates, and an evaluation reads the bins
+    whose cut lies below its larger rate.  Points and intervals whose larger
+    rate sits just below, at and just above each cut (and intervals that start
+    there) give the oracle's S, N, S_bar, N_low and every image cell."""
+    from paper_2209_13168_amd import ecmd
+    from synth import config_windows
+
+    w = config_windows("c5", [7], n_events=150_000)[0]
+    s = w.spec
+    sen = ecmd.sensor(s.width, s.height, s.foe)
+    ev = orc.Events.of_window(w)
+    M = s.width * s.height
+    r_lo, r_hi = _rate32(s.d_lo, s.tau), _rate32(s.d_hi, s.tau)
+    assert r_lo == 0.0  # the cuts are then exact multiples of r_hi / 4
+    ends = []
+    for m in (1, 2, 3):
+        cut = np.float32(np.float32(m / 4.0) * r_hi)
+        ends += _ds_around_rate(cut, s.tau)
+    ends = np.array(ends, np.float32)
+    S, N, img = ctx.probe_point(sen, w.x, w.y, w.t_rel, s.tau, ends, want_image=True)
+    for k, d in enumerate(ends):
+        So, No, Ho = orc.point(ev, float(d), want_image=True)
+        assert (int(S[k]), int(N[k])) == (So, No), (k, d)
+        assert np.array_equal(img[k * M:(k + 1) * M], Ho), (k, d)
+    da, db = [], []
+    for d in ends:
+        for width in (1e-4, 0.02):
+            da.append(max(s.d_lo, float(d) - width))
+            db.append(float(d))
+        da.append(float(d))
+        db.append(min(s.d_hi, float(d) + 0.01))
+    da, db = np.array(da, np.float32), np.array(db, np.float32)
+    Sb, Nl, img = ctx.probe_bound(sen, w.x, w.y, w.t_rel, s.tau, s.d_lo, s.d_hi, da, db, want_image=True)
+    for k in range(da.size):
+        So, No, Ho = orc.bound(ev, float(da[k]), float(db[k]), want_image=True)
+        assert (int(Sb[k]), int(Nl[k])) == (So, No), (k, da[k], db[k])
+        assert np.array_equal(img[k * M:(k + 1) * M], Ho), (k, da[k], db[k])
