@@ -324,7 +324,8 @@ int ecmd_estimate_stream(ecmd_ctx *ctx, const ecmd_sensor *sensor, const ecmd_ev
  *   max_steps:   frontier steps per launch, rounded up to a multiple of 4
  *                (0 = 2L + 8 for the grid depth L, e.g. 44 for L = 18; a
  *                search of F nodes per step usually needs about L steps);
- *                each costs two kernel launches, which return at once for
+ *                each costs four kernel launches (two evaluations and
+ *                the two frontier phases), which return at once for
  *                finished windows;
  *   max_events:  events of a launch over all windows, 1 .. 2^40;
  *   max_records: binned event records, guest copies included (0 = the worst
